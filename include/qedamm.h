@@ -1,0 +1,148 @@
+/*
+ * qedamm.h -- C ABI of the MI355X hot path for the per-graph Monte Carlo
+ * integration of the IR/UV-subtracted Feynman-parametric integrand of QED
+ * vertex graphs without lepton loops (S. Volkov, 5-loop electron AMM).
+ *
+ * Conventions for every entry point
+ *   - returns QA_OK (0) or a negative QA_E* code; qa_last_error() gives a
+ *     thread-local message.  No C++ exception crosses this boundary.
+ *   - "host" pointers are ordinary CPU memory owned by the caller; "device"
+ *     pointers are HIP device memory owned by the caller (the library never
+ *     allocates device memory in these calls, except where stated).
+ *   - stream arguments are hipStream_t passed as void* (NULL = null stream);
+ *     kernels are enqueued asynchronously; launch errors are returned, errors
+ *     inside kernels surface at the next synchronising call.
+ *   - handles (qa_set*, qa_pdf*) are immutable after creation and may be
+ *     shared between threads.
+ */
+#ifndef QEDAMM_H
+#define QEDAMM_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { QA_OK = 0, QA_EINVAL = -1, QA_ECAP = -2, QA_EHIP = -3, QA_ENOTSUP = -4, QA_ENOMEM = -5 };
+enum { QA_FP64 = 0, QA_FP64_BOUND = 1, QA_DD = 2 };  /* eval_integrand modes */
+
+/* A vertex graph without lepton loops at n loops: an open electron line with
+ * slots 0..2n, the external photon at slot x, mate[s] = partner slot of the
+ * internal photon at s (mate[x] = x).  mult = 1 if the graph equals its
+ * reversal, else 2 (arrow reversal identified, footnote to Table 1).
+ * cls = (k, m, n): photons crossing x, and max / min of the photons entirely
+ * left / right of x (classes of Table 1).  Lines: electron line i joins slots
+ * i and i+1 (i < 2n); photon line 2n+a is the a-th photon by lower end. */
+typedef struct qa_graph {
+    int32_t loops;
+    int32_t x;
+    int8_t mate[12];
+    int32_t mult;
+    int32_t cls[3];
+} qa_graph;
+
+/* Per-graph Monte Carlo sums: N samples, S1 = sum of w = f/p and S2 = sum of
+ * w^2, each as an unevaluated double-double (hi + lo).  Device layout. */
+typedef struct qa_acc {
+    uint64_t n;
+    double s1_hi, s1_lo;
+    double s2_hi, s2_lo;
+    uint64_t n_flagged;   /* points recomputed in double-double */
+    uint64_t n_bad;       /* non-finite or underflowed points, excluded */
+} qa_acc;
+
+typedef struct qa_set qa_set;   /* graphs + forests + integrand tables (host) */
+typedef struct qa_pdf qa_pdf;   /* Deg and W tables of eq. (1) (host) */
+
+const char* qa_last_error(void);
+
+/* Enumerate the canonical representatives at `loops` (1..5) loops in their
+ * canonical order (ascending (x, mate[0..2n]) key, each graph the smaller key
+ * of itself and its reversal).  (k, m, n) filters the class; -1 = any; m and
+ * n are unordered.  Writes at most cap records to out (host); *count receives
+ * the total.  QA_ECAP if cap is too small (count still set).
+ * Paper: "all 3213 integrands"; Table 1 N_diag; section "The method". */
+int qa_enumerate_graphs(int loops, int k, int m, int n, qa_graph* out, size_t cap, size_t* count);
+
+/* Build the UV-divergent 1PI subgraphs, the forests, the forest-formula terms
+ * and the projected-numerator coefficient tables for ng graphs (host input,
+ * copied).  Section "The method": point-wise subtraction by a forest-like
+ * formula of linear operators on UV-divergent subdiagrams.  nthreads <= 0:
+ * use all host cores for the table build.  *out receives a new handle. */
+int qa_build_forests(const qa_graph* g, size_t ng, int nthreads, qa_set** out);
+void qa_set_destroy(qa_set* s);
+
+/* Canonical byte serialisation of the subgraph and forest lists of every
+ * graph (for bit-exact comparison): per graph the int32 sequence
+ *   nsub, (lo, hi, kind 0=vertex 1=self-energy, has_x) * nsub,
+ *   nforest, mask * nforest, nterm, (mask, apos) * nterm.
+ * QA_ECAP if cap is too small; *len receives the byte length. */
+int qa_forests_serialize(const qa_set* s, void* buf, size_t cap, size_t* len);
+
+/* Statistics of the coefficient tables: monomial blocks, coefficients, terms. */
+int qa_set_stats(const qa_set* s, uint64_t* nterms, uint64_t* nblocks, uint64_t* ncoef);
+
+/* Deg and W tables of eq. (1) for every graph of the set.  deg == NULL: the
+ * default Deg rule (parametric UV degree of the I-closure, minimised over the
+ * reduced graphs of all forests, floored at 1/2).  Otherwise deg holds, for
+ * graph i, 2^(3 n) doubles at offset sum_{j<i} 2^(3 n_j) (entries 0 and full
+ * ignored, all others must be > 0).  W(S) = Deg(S)^-1 sum_j W(S\j),
+ * W(full) = sum_j W(full\j). */
+int qa_pdf_create(const qa_set* s, const double* deg, qa_pdf** out);
+void qa_pdf_destroy(qa_pdf* p);
+/* Copy graph i's Deg and W tables (2^(3n) doubles each; either may be NULL). */
+int qa_pdf_tables(const qa_pdf* p, uint32_t graph, double* deg, double* w);
+/* Gradient of ln W(full) with respect to Deg(S) for graph i (2^(3n) doubles). */
+int qa_pdf_dlogw(const qa_pdf* p, uint32_t graph, double* out);
+
+/* Size of the device image holding the set's tables and the pdf tables. */
+int qa_device_bytes(const qa_set* s, const qa_pdf* p, size_t* bytes);
+/* Copy the image into the caller's device buffer dev (>= qa_device_bytes). */
+int qa_upload(const qa_set* s, const qa_pdf* p, void* dev, size_t bytes, void* stream);
+
+/* Draw points of graph `graph` from its sector PDF, eq. (1): Philox4x32-10
+ * with key (seed, tag) and counter (block, graph, sample lo, sample hi),
+ * samples first .. first+count-1.  Outputs (device): z SoA [M][count]
+ * (z[l*count + i]), logp[count] = ln p(z) w.r.t. d^(M-1)z, sector (nullable)
+ * SoA [M][count] bytes: j_1..j_M (z_{j1} >= ... >= z_{jM}). */
+int qa_sample_pdf(const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, uint64_t first,
+                  uint64_t count, double* z, double* logp, uint8_t* sector, void* stream);
+
+/* Evaluate f_G(z) for count points (device, SoA [M][count], any positive
+ * scale: f is homogeneous of degree -M and is evaluated at z / sum z).
+ * mode QA_FP64: f only.  QA_FP64_BOUND: also err[i] = running error bound and
+ * flag[i] = 1 if err > 1e-11 |f|.  QA_DD: double-double evaluation, err = its
+ * bound.  err and flag may be NULL for QA_FP64.  Units: (alpha/pi)^n. */
+int qa_eval_integrand(const void* dev, uint32_t graph, const double* z, uint64_t count, int mode,
+                      double* f, double* err, uint8_t* flag, void* stream);
+
+/* acc (device, one record) += the samples w = f * exp(-logp) (device arrays
+ * of count doubles) with compensated (double-double) sums; non-finite w are
+ * counted in n_bad and skipped. */
+int qa_accumulate(const double* f, const double* logp, uint64_t count, qa_acc* acc, void* stream);
+
+/* Batched form: all graphs of the set with per-graph budgets (host array,
+ * samples per graph, first sample index 0), fused sample + evaluate (FP64
+ * with error bound) + accumulate in one persistent launch, flagged points
+ * recomputed in double-double, deterministic per-tile partials reduced into
+ * acc (device, ng records, overwritten).  work (device) >= qa_work_bytes.
+ * tile = samples per tile (multiple of 64, 0 = default). */
+int qa_work_bytes(const qa_set* s, const uint64_t* budgets, uint32_t tile, size_t* bytes);
+int qa_integrate(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t seed, uint32_t tag,
+                 uint32_t tile, uint32_t grid, void* work, size_t work_bytes, qa_acc* acc, void* stream);
+
+/* Variance gradient (pilot runs): for graph `graph`, samples first..first+
+ * count-1 of stream (seed, tag): grad (device, 2^M doubles, accumulated +=)
+ * receives sum_i w_i^2 sum_l t_l [S_l = S]; w2sum (device, 1 double) += sum
+ * w_i^2.  d Var / d Deg(S) = grad[S]/N + (w2sum/N) dlnW/dDeg(S). */
+int qa_variance_grad(const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, uint64_t first,
+                     uint64_t count, double* grad, double* w2sum, void* stream);
+
+/* Debug / test hook: exact Dirac trace of a symbol string (0 = on-shell
+ * p-slash with p.p = 1; L > 0 = gamma contracted with the other L). */
+int qa_dirac_trace(const int32_t* sym, int len, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,288 @@
+"""MI355X hot path of Volkov's 5-loop QED AMM method: per-sample evaluation
+of the IR/UV-subtracted Feynman-parametric integrand of vertex graphs without
+lepton loops, at points from each graph's Hepp-sector PDF, accumulated into
+per-graph value and variance sums.
+
+This module is the argument-marshalling layer over the C ABI of
+``libqedamm.so`` (declared in ``include/qedamm.h``); every step of the path
+runs in the library's HIP kernels.  PyTorch provides device memory and
+streams.  Importing succeeds without the library; every call that needs it
+raises ``RuntimeError`` when it is missing (there is no CPU fallback).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqedamm.so")
+
+QA_FP64, QA_FP64_BOUND, QA_DD = 0, 1, 2
+
+
+class QaGraph(C.Structure):
+    _fields_ = [("loops", C.c_int32), ("x", C.c_int32), ("mate", C.c_int8 * 12),
+                ("mult", C.c_int32), ("cls", C.c_int32 * 3)]
+
+
+ACC_DTYPE = np.dtype([("n", "<u8"), ("s1_hi", "<f8"), ("s1_lo", "<f8"), ("s2_hi", "<f8"),
+                      ("s2_lo", "<f8"), ("n_flagged", "<u8"), ("n_bad", "<u8")])
+ACC_BYTES = ACC_DTYPE.itemsize  # 56
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1905_08007_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, sz, u64, u32, i32 = C.c_void_p, C.c_size_t, C.c_uint64, C.c_uint32, C.c_int
+        L.qa_last_error.restype = C.c_char_p
+        L.qa_enumerate_graphs.argtypes = [i32, i32, i32, i32, vp, sz, C.POINTER(sz)]
+        L.qa_build_forests.argtypes = [vp, sz, i32, C.POINTER(vp)]
+        L.qa_set_destroy.argtypes = [vp]
+        L.qa_set_destroy.restype = None
+        L.qa_forests_serialize.argtypes = [vp, vp, sz, C.POINTER(sz)]
+        L.qa_set_stats.argtypes = [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]
+        L.qa_pdf_create.argtypes = [vp, vp, C.POINTER(vp)]
+        L.qa_pdf_destroy.argtypes = [vp]
+        L.qa_pdf_destroy.restype = None
+        L.qa_pdf_tables.argtypes = [vp, u32, vp, vp]
+        L.qa_pdf_dlogw.argtypes = [vp, u32, vp]
+        L.qa_device_bytes.argtypes = [vp, vp, C.POINTER(sz)]
+        L.qa_upload.argtypes = [vp, vp, vp, sz, vp]
+        L.qa_sample_pdf.argtypes = [vp, u32, u64, u32, u64, u64, vp, vp, vp, vp]
+        L.qa_eval_integrand.argtypes = [vp, u32, vp, u64, i32, vp, vp, vp, vp]
+        L.qa_accumulate.argtypes = [vp, vp, u64, vp, vp]
+        L.qa_work_bytes.argtypes = [vp, vp, u32, C.POINTER(sz)]
+        L.qa_integrate.argtypes = [vp, vp, vp, u64, u32, u32, u32, vp, sz, vp, vp]
+        L.qa_variance_grad.argtypes = [vp, u32, u64, u32, u64, u64, vp, vp, vp]
+        L.qa_dirac_trace.argtypes = [vp, i32, C.POINTER(C.c_double)]
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = lib().qa_last_error().decode(errors="replace")
+        raise RuntimeError(f"{what} failed ({rc}): {msg}")
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------------------- graphs
+
+def enumerate_graphs(loops, k=-1, m=-1, n=-1):
+    """Canonical representatives (numpy structured array of qa_graph)."""
+    cnt = C.c_size_t()
+    rc = lib().qa_enumerate_graphs(loops, k, m, n, None, 0, C.byref(cnt))
+    if rc not in (0, -2):
+        _check(rc, "qa_enumerate_graphs")
+    arr = (QaGraph * max(1, cnt.value))()
+    _check(lib().qa_enumerate_graphs(loops, k, m, n, arr, cnt.value, C.byref(cnt)), "qa_enumerate_graphs")
+    return list(arr)[:cnt.value]
+
+
+def graph_dict(g):
+    n = g.loops
+    return {"n": n, "x": g.x, "mate": list(g.mate[:2 * n + 1]), "mult": g.mult, "cls": tuple(g.cls)}
+
+
+class GraphSet:
+    """qa_set handle: graphs, subgraphs, forests and coefficient tables."""
+
+    def __init__(self, graphs, nthreads=0):
+        self.graphs = list(graphs)
+        arr = (QaGraph * len(self.graphs))(*self.graphs)
+        h = C.c_void_p()
+        _check(lib().qa_build_forests(arr, len(self.graphs), nthreads, C.byref(h)), "qa_build_forests")
+        self.h = h
+
+    def __len__(self):
+        return len(self.graphs)
+
+    def serialize(self):
+        ln = C.c_size_t()
+        lib().qa_forests_serialize(self.h, None, 0, C.byref(ln))
+        buf = C.create_string_buffer(ln.value)
+        _check(lib().qa_forests_serialize(self.h, buf, ln.value, C.byref(ln)), "qa_forests_serialize")
+        return np.frombuffer(buf.raw, dtype="<i4").copy()
+
+    def stats(self):
+        a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(lib().qa_set_stats(self.h, C.byref(a), C.byref(b), C.byref(c)), "qa_set_stats")
+        return {"terms": a.value, "blocks": b.value, "coefficients": c.value}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.qa_set_destroy(self.h)
+            self.h = None
+
+
+def build_forests(graphs, nthreads=0):
+    return GraphSet(graphs, nthreads)
+
+
+class Pdf:
+    """qa_pdf handle: Deg and W tables of eq. (1)."""
+
+    def __init__(self, gset, deg=None):
+        self.gset = gset
+        h = C.c_void_p()
+        dptr = None
+        if deg is not None:
+            self._deg = np.ascontiguousarray(np.concatenate([np.asarray(d, dtype=np.float64) for d in deg]))
+            dptr = self._deg.ctypes.data_as(C.c_void_p)
+        _check(lib().qa_pdf_create(gset.h, dptr, C.byref(h)), "qa_pdf_create")
+        self.h = h
+
+    def tables(self, g):
+        M = 3 * self.gset.graphs[g].loops
+        D = np.zeros(1 << M)
+        W = np.zeros(1 << M)
+        _check(lib().qa_pdf_tables(self.h, g, D.ctypes.data_as(C.c_void_p), W.ctypes.data_as(C.c_void_p)),
+               "qa_pdf_tables")
+        return D, W
+
+    def dlogw(self, g):
+        M = 3 * self.gset.graphs[g].loops
+        out = np.zeros(1 << M)
+        _check(lib().qa_pdf_dlogw(self.h, g, out.ctypes.data_as(C.c_void_p)), "qa_pdf_dlogw")
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.qa_pdf_destroy(self.h)
+            self.h = None
+
+
+def pdf_create(gset, deg=None):
+    return Pdf(gset, deg)
+
+
+class DeviceImage:
+    """Device copy of the set's tables and the pdf (caller-owned torch buffer)."""
+
+    def __init__(self, gset, pdf, device="cuda", stream=None):
+        import torch
+        n = C.c_size_t()
+        _check(lib().qa_device_bytes(gset.h, pdf.h, C.byref(n)), "qa_device_bytes")
+        self.buf = torch.empty(n.value, dtype=torch.uint8, device=device)
+        self.gset, self.pdf = gset, pdf
+        _check(lib().qa_upload(gset.h, pdf.h, _ptr(self.buf), n.value, _stream(stream)), "qa_upload")
+
+    @property
+    def ptr(self):
+        return _ptr(self.buf)
+
+
+def upload(gset, pdf, device="cuda", stream=None):
+    return DeviceImage(gset, pdf, device, stream)
+
+
+# --------------------------------------------------------------------------- hot path
+
+def sample_pdf(img, graph, seed, tag, first, count, want_sector=False, stream=None):
+    import torch
+    M = 3 * img.gset.graphs[graph].loops
+    dev = img.buf.device
+    z = torch.empty((M, count), dtype=torch.float64, device=dev)
+    logp = torch.empty(count, dtype=torch.float64, device=dev)
+    sec = torch.empty((M, count), dtype=torch.uint8, device=dev) if want_sector else None
+    _check(lib().qa_sample_pdf(img.ptr, graph, seed, tag, first, count, _ptr(z), _ptr(logp), _ptr(sec),
+                               _stream(stream)), "qa_sample_pdf")
+    return z, logp, sec
+
+
+def eval_integrand(img, graph, z, mode=QA_FP64, stream=None):
+    import torch
+    M, count = z.shape
+    assert M == 3 * img.gset.graphs[graph].loops and z.dtype == torch.float64 and z.is_contiguous()
+    f = torch.empty(count, dtype=torch.float64, device=z.device)
+    err = torch.empty(count, dtype=torch.float64, device=z.device) if mode != QA_FP64 else None
+    flag = torch.empty(count, dtype=torch.uint8, device=z.device) if mode == QA_FP64_BOUND else None
+    _check(lib().qa_eval_integrand(img.ptr, graph, _ptr(z), count, mode, _ptr(f), _ptr(err), _ptr(flag),
+                                   _stream(stream)), "qa_eval_integrand")
+    return f, err, flag
+
+
+def new_acc(ngraphs, device="cuda"):
+    import torch
+    return torch.zeros(ngraphs * ACC_BYTES, dtype=torch.uint8, device=device)
+
+
+def accumulate(f, logp, acc, index=0, stream=None):
+    ptr = C.c_void_p(acc.data_ptr() + index * ACC_BYTES)
+    _check(lib().qa_accumulate(_ptr(f), _ptr(logp), f.numel(), ptr, _stream(stream)), "qa_accumulate")
+
+
+def read_acc(acc):
+    return np.frombuffer(acc.cpu().numpy().tobytes(), dtype=ACC_DTYPE)
+
+
+def estimates(acc_np, mults):
+    """(value, sigma) per graph: mult * S1/N and mult * sqrt((S2/N - (S1/N)^2)/(N-1))."""
+    out = []
+    for a, mu in zip(acc_np, mults):
+        n = int(a["n"])
+        s1 = float(a["s1_hi"]) + float(a["s1_lo"])
+        s2 = float(a["s2_hi"]) + float(a["s2_lo"])
+        mean = s1 / n
+        var = (s2 / n - mean * mean) / (n - 1)
+        out.append((mu * mean, mu * float(np.sqrt(max(var, 0.0)))))
+    return out
+
+
+def work_bytes(gset, budgets, tile=0):
+    b = np.ascontiguousarray(budgets, dtype=np.uint64)
+    n = C.c_size_t()
+    _check(lib().qa_work_bytes(gset.h, b.ctypes.data_as(C.c_void_p), tile, C.byref(n)), "qa_work_bytes")
+    return n.value
+
+
+def integrate(gset, img, budgets, seed, tag=0, tile=0, grid=0, work=None, acc=None, stream=None):
+    """Batched form: one persistent launch per round under a hipGraph."""
+    import torch
+    b = np.ascontiguousarray(budgets, dtype=np.uint64)
+    dev = img.buf.device
+    if work is None:
+        work = torch.empty(work_bytes(gset, b, tile), dtype=torch.uint8, device=dev)
+    if acc is None:
+        acc = new_acc(len(gset), dev)
+    _check(lib().qa_integrate(gset.h, img.ptr, b.ctypes.data_as(C.c_void_p), seed, tag, tile, grid, _ptr(work),
+                              work.numel(), _ptr(acc), _stream(stream)), "qa_integrate")
+    return acc
+
+
+def variance_grad(img, graph, seed, tag, first, count, grad=None, w2sum=None, stream=None):
+    import torch
+    M = 3 * img.gset.graphs[graph].loops
+    dev = img.buf.device
+    if grad is None:
+        grad = torch.zeros(1 << M, dtype=torch.float64, device=dev)
+    if w2sum is None:
+        w2sum = torch.zeros(1, dtype=torch.float64, device=dev)
+    _check(lib().qa_variance_grad(img.ptr, graph, seed, tag, first, count, _ptr(grad), _ptr(w2sum),
+                                  _stream(stream)), "qa_variance_grad")
+    return grad, w2sum
+
+
+def dirac_trace(symbols):
+    arr = (C.c_int32 * len(symbols))(*symbols)
+    out = C.c_double()
+    _check(lib().qa_dirac_trace(arr, len(symbols), C.byref(out)), "qa_dirac_trace")
+    return out.value
+
+
+from .autograd import VarianceFn, variance_and_grad  # noqa: E402,F401

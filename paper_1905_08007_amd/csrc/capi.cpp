@@ -1,0 +1,408 @@
+// C ABI: handles, error reporting and packing of the device image.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <thread>
+
+#include "../../include/qedamm.h"
+#include "host.h"
+
+using namespace qa;
+
+static thread_local std::string g_err;
+static int fail(int code, const std::string& msg) { g_err = msg; return code; }
+int qa_fail(int code, const std::string& msg) { return fail(code, msg); }
+extern "C" const char* qa_last_error(void) { return g_err.c_str(); }
+
+struct qa_set {
+    std::vector<GraphTables> graphs;
+};
+struct qa_pdf {
+    std::vector<int> M;
+    std::vector<std::vector<double>> deg, w;
+};
+
+static Graph from_c(const qa_graph& c) {
+    Graph g{};
+    g.n = c.loops; g.x = c.x; g.mult = c.mult;
+    for (int i = 0; i < 12; ++i) g.mate[i] = c.mate[i];
+    for (int i = 0; i < 3; ++i) g.cls[i] = c.cls[i];
+    return g;
+}
+
+extern "C" int qa_enumerate_graphs(int loops, int k, int m, int n, qa_graph* out, size_t cap, size_t* count) {
+    try {
+        if (loops < 1 || loops > QA_MAXN) return fail(QA_EINVAL, "loops must be 1..5");
+        if (!count) return fail(QA_EINVAL, "count is NULL");
+        auto all = enumerate(loops);
+        size_t c = 0;
+        for (auto& g : all) {
+            if (k >= 0 && g.cls[0] != k) continue;
+            if (m >= 0 || n >= 0) {
+                int mm = std::max(m, n), nn = std::min(m, n);
+                if (m < 0 || n < 0) { if (g.cls[1] != mm && g.cls[2] != mm) continue; }
+                else if (g.cls[1] != mm || g.cls[2] != nn) continue;
+            }
+            if (c < cap && out) {
+                qa_graph& o = out[c];
+                std::memset(&o, 0, sizeof o);
+                o.loops = g.n; o.x = g.x; o.mult = g.mult;
+                for (int s = 0; s <= 2 * g.n; ++s) o.mate[s] = (int8_t)g.mate[s];
+                for (int i = 0; i < 3; ++i) o.cls[i] = g.cls[i];
+            }
+            ++c;
+        }
+        *count = c;
+        if (c > cap) return fail(QA_ECAP, "output capacity too small");
+        return QA_OK;
+    } catch (std::exception& e) { return fail(QA_EINVAL, e.what()); }
+}
+
+// structure of one graph (fast); the tables are filled by build_tables
+static void build_structure(GraphTables& T) {
+    const Graph& g = T.g;
+    T.subs = subgraphs(g);
+    T.forests = forests(T.subs);
+    T.terms = terms(T.subs);
+    for (auto& tm : T.terms) {
+        auto pcs = term_pieces(g, T.subs, tm.first, tm.second);
+        std::vector<std::vector<Table>> tabs;
+        for (auto& p : pcs) {
+            int nins = 0;
+            for (auto& nd : p.nodes) nins += nd.vtype == 2;
+            int nop = p.op == QA_OP_US ? 2 : 1;
+            tabs.push_back(std::vector<Table>((size_t)nop << nins));
+        }
+        T.pieces.push_back(std::move(pcs));
+        T.tabs.push_back(std::move(tabs));
+    }
+}
+
+extern "C" int qa_build_forests(const qa_graph* gs, size_t ng, int nthreads, qa_set** out) {
+    try {
+        if (!gs || !out) return fail(QA_EINVAL, "NULL argument");
+        auto* s = new qa_set;
+        s->graphs.resize(ng);
+        for (size_t i = 0; i < ng; ++i) {
+            if (gs[i].loops < 1 || gs[i].loops > QA_MAXN) { delete s; return fail(QA_EINVAL, "bad loops"); }
+            s->graphs[i].g = from_c(gs[i]);
+            build_structure(s->graphs[i]);
+        }
+        // jobs: slices of coefficient tables (large tables split by block
+        // index mod nparts), largest first; slices are merged in block order
+        struct Job { size_t g, t, p, v; int part, nparts; size_t cost; };
+        std::vector<Job> jobs;
+        for (size_t gi = 0; gi < ng; ++gi) {
+            auto& T = s->graphs[gi];
+            for (size_t ti = 0; ti < T.terms.size(); ++ti)
+                for (size_t pi = 0; pi < T.pieces[ti].size(); ++pi) {
+                    const size_t nl = T.pieces[ti][pi].lines.size();
+                    const int np = nl >= 9 ? 32 : (nl >= 7 ? 4 : 1);
+                    for (size_t v = 0; v < T.tabs[ti][pi].size(); ++v)
+                        for (int part = 0; part < np; ++part) jobs.push_back({gi, ti, pi, v, part, np, nl});
+                }
+        }
+        std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) { return a.cost > b.cost; });
+        std::vector<Table> slices(jobs.size());
+        int nt = nthreads > 0 ? nthreads : (int)std::thread::hardware_concurrency();
+        nt = std::max(1, std::min<int>(nt, (int)jobs.size()));
+        std::atomic<size_t> next{0};
+        std::string err;
+        std::mutex mu;
+        std::vector<std::thread> th;
+        for (int t = 0; t < nt; ++t)
+            th.emplace_back([&] {
+                for (size_t i; (i = next++) < jobs.size();) {
+                    const Job& j = jobs[i];
+                    auto& T = s->graphs[j.g];
+                    const Piece& pc = T.pieces[j.t][j.p];
+                    const size_t nvar = T.tabs[j.t][j.p].size();
+                    const int nop = pc.op == QA_OP_US ? 2 : 1;
+                    const size_t per = nvar / nop;
+                    try { slices[i] = build_table(pc, (int)(j.v / per), (uint32_t)(j.v % per), T.g.n, j.part, j.nparts); }
+                    catch (std::exception& e) { std::lock_guard<std::mutex> l(mu); err = e.what(); }
+                }
+            });
+        for (auto& t : th) t.join();
+        // merge slices: blocks are interleaved by index mod nparts within each k
+        std::map<std::array<size_t, 4>, std::vector<size_t>> parts;
+        for (size_t i = 0; i < jobs.size(); ++i) parts[{jobs[i].g, jobs[i].t, jobs[i].p, jobs[i].v}].push_back(i);
+        for (auto& kv : parts) {
+            auto& idx = kv.second;
+            std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return jobs[a].part < jobs[b].part; });
+            Table merged = slices[idx[0]];
+            merged.blocks.clear();
+            std::vector<size_t> pos(idx.size(), 0);
+            for (int k = 0; k <= QA_MAXN; ++k) {
+                // round-robin over slices, blocks of this k, restores enumeration order of the kept blocks
+                std::vector<std::vector<const Block*>> per(idx.size());
+                for (size_t q = 0; q < idx.size(); ++q)
+                    for (auto& b : slices[idx[q]].blocks) if (b.k == k) per[q].push_back(&b);
+                size_t maxlen = 0;
+                for (auto& v : per) maxlen = std::max(maxlen, v.size());
+                for (size_t r = 0; r < maxlen; ++r)
+                    for (size_t q = 0; q < idx.size(); ++q)
+                        if (r < per[q].size()) merged.blocks.push_back(*per[q][r]);
+            }
+            s->graphs[kv.first[0]].tabs[kv.first[1]][kv.first[2]][kv.first[3]] = std::move(merged);
+        }
+        if (!err.empty()) { delete s; return fail(QA_EINVAL, err); }
+        *out = s;
+        return QA_OK;
+    } catch (std::exception& e) { return fail(QA_ENOMEM, e.what()); }
+}
+
+extern "C" void qa_set_destroy(qa_set* s) { delete s; }
+
+extern "C" int qa_forests_serialize(const qa_set* s, void* buf, size_t cap, size_t* len) {
+    if (!s || !len) return fail(QA_EINVAL, "NULL argument");
+    std::vector<int32_t> v;
+    for (auto& T : s->graphs) {
+        v.push_back((int32_t)T.subs.size());
+        for (auto& x : T.subs) { v.push_back(x.lo); v.push_back(x.hi); v.push_back(x.kind); v.push_back(x.has_x); }
+        v.push_back((int32_t)T.forests.size());
+        for (auto f : T.forests) v.push_back((int32_t)f);
+        v.push_back((int32_t)T.terms.size());
+        for (auto& t : T.terms) { v.push_back((int32_t)t.first); v.push_back(t.second); }
+    }
+    *len = v.size() * 4;
+    if (!buf || cap < *len) return fail(QA_ECAP, "buffer too small");
+    std::memcpy(buf, v.data(), *len);
+    return QA_OK;
+}
+
+extern "C" int qa_set_stats(const qa_set* s, uint64_t* nterms, uint64_t* nblocks, uint64_t* ncoef) {
+    if (!s) return fail(QA_EINVAL, "NULL set");
+    uint64_t a = 0, b = 0, c = 0;
+    for (auto& T : s->graphs) {
+        a += T.terms.size();
+        for (auto& tv : T.tabs) for (auto& pv : tv) for (auto& tb : pv) {
+            b += tb.blocks.size();
+            for (auto& bl : tb.blocks) c += bl.coef.size();
+        }
+    }
+    if (nterms) *nterms = a;
+    if (nblocks) *nblocks = b;
+    if (ncoef) *ncoef = c;
+    return QA_OK;
+}
+
+extern "C" int qa_pdf_create(const qa_set* s, const double* deg, qa_pdf** out) {
+    try {
+        if (!s || !out) return fail(QA_EINVAL, "NULL argument");
+        auto* p = new qa_pdf;
+        size_t off = 0;
+        for (auto& T : s->graphs) {
+            int M = 3 * T.g.n;
+            std::vector<double> D;
+            if (deg) {
+                D.assign(deg + off, deg + off + (size_t(1) << M));
+                for (uint32_t x = 1; x + 1 < (1u << M); ++x)
+                    if (!(D[x] > 0.0) || !std::isfinite(D[x])) { delete p; return fail(QA_EINVAL, "Deg entries must be positive"); }
+                D[0] = 0.0; D[(1u << M) - 1] = 0.0;
+            } else D = default_deg(T.g);
+            off += size_t(1) << M;
+            p->M.push_back(M);
+            p->w.push_back(w_table(D, M));
+            p->deg.push_back(std::move(D));
+        }
+        *out = p;
+        return QA_OK;
+    } catch (std::exception& e) { return fail(QA_ENOMEM, e.what()); }
+}
+
+extern "C" void qa_pdf_destroy(qa_pdf* p) { delete p; }
+
+extern "C" int qa_pdf_tables(const qa_pdf* p, uint32_t graph, double* deg, double* w) {
+    if (!p || graph >= p->M.size()) return fail(QA_EINVAL, "bad graph index");
+    size_t n = size_t(1) << p->M[graph];
+    if (deg) std::memcpy(deg, p->deg[graph].data(), n * 8);
+    if (w) std::memcpy(w, p->w[graph].data(), n * 8);
+    return QA_OK;
+}
+
+extern "C" int qa_pdf_dlogw(const qa_pdf* p, uint32_t graph, double* out) {
+    if (!p || graph >= p->M.size() || !out) return fail(QA_EINVAL, "bad argument");
+    auto d = dlogw(p->deg[graph], p->M[graph]);
+    std::memcpy(out, d.data(), d.size() * 8);
+    return QA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device image
+
+namespace {
+struct Packer {
+    std::vector<uint8_t> buf;
+    uint64_t alloc(size_t bytes, size_t align = 16) {
+        size_t off = (buf.size() + align - 1) / align * align;
+        buf.resize(off + bytes, 0);
+        return off;
+    }
+    template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(buf.data() + off); }
+};
+}  // namespace
+
+static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
+    if (!s || !p || p->M.size() != s->graphs.size()) return fail(QA_EINVAL, "set / pdf mismatch");
+    Packer P;
+    uint64_t h = P.alloc(sizeof(DevHeader), 256);
+    uint64_t goff = P.alloc(sizeof(DevGraph) * s->graphs.size(), 256);
+    {
+        auto* hd = P.at<DevHeader>(h);
+        hd->magic = 0x51454441u; hd->version = 1; hd->ngraphs = (uint32_t)s->graphs.size(); hd->graphs_off = goff;
+    }
+    for (size_t gi = 0; gi < s->graphs.size(); ++gi) {
+        const auto& T = s->graphs[gi];
+        const int M = 3 * T.g.n;
+        uint64_t doff = P.alloc(8u << M, 256);
+        std::memcpy(P.buf.data() + doff, p->deg[gi].data(), 8u << M);
+        uint64_t woff = P.alloc(8u << M, 256);
+        std::memcpy(P.buf.data() + woff, p->w[gi].data(), 8u << M);
+        uint64_t toff = P.alloc(sizeof(DevTerm) * T.terms.size(), 64);
+        int npoly_max = 0;
+        for (size_t ti = 0; ti < T.terms.size(); ++ti) {
+            const auto& pcs = T.pieces[ti];
+            uint64_t poff = P.alloc(sizeof(DevPiece) * pcs.size(), 64);
+            {
+                auto* dt = P.at<DevTerm>(toff + ti * sizeof(DevTerm));
+                int nf = __builtin_popcount(T.terms[ti].first);
+                dt->sign = ((nf + T.g.n) % 2) ? -1 : 1;
+                dt->npieces = (int)pcs.size();
+                dt->pieces_off = poff;
+            }
+            // result slots: free list
+            std::vector<int> slot_of(pcs.size(), -1);
+            std::vector<int> busy(QA_MAXPOLY, 0);
+            auto grab = [&](int w) {
+                for (int s0 = 0; s0 + w <= QA_MAXPOLY; ++s0) {
+                    bool ok = true;
+                    for (int q = 0; q < w; ++q) ok &= !busy[s0 + q];
+                    if (ok) { for (int q = 0; q < w; ++q) busy[s0 + q] = 1; return s0; }
+                }
+                throw std::runtime_error("too many live polynomials");
+            };
+            for (size_t pi = 0; pi < pcs.size(); ++pi) {
+                const Piece& pc = pcs[pi];
+                DevPiece dp{};
+                dp.op = pc.op;
+                dp.nlines = (int)pc.lines.size();
+                dp.nchords = (int)pc.chords.size();
+                dp.ext = pc.ext;
+                if (dp.nlines > QA_MAXL || dp.nchords > QA_MAXC) throw std::runtime_error("piece too large");
+                for (int i = 0; i < dp.nlines; ++i) dp.line_id[i] = pc.lines[i];
+                for (int c = 0; c < dp.nchords; ++c) {
+                    dp.chord_photon[c] = 2 * T.g.n + pc.chords[c][0];
+                    dp.chord_lo[c] = pc.chords[c][1];
+                    dp.chord_hi[c] = pc.chords[c][2];
+                }
+                auto piece_of = [&](int sub) {
+                    for (size_t q = 0; q < pcs.size(); ++q) if (pcs[q].elem == sub) return (int)q;
+                    throw std::runtime_error("child piece missing");
+                };
+                dp.nins = 0; dp.nvkids = 0;
+                for (auto& nd : pc.nodes) {
+                    if (nd.kid < 0) continue;
+                    int q = piece_of(nd.kid);
+                    if (nd.vtype == 2) dp.ins_slot[dp.nins++] = slot_of[q];
+                    else dp.vkid_slot[dp.nvkids++] = slot_of[q];
+                }
+                // children's results are consumed here: free them, then grab ours
+                for (auto& nd : pc.nodes) {
+                    if (nd.kid < 0) continue;
+                    int q = piece_of(nd.kid);
+                    int w = pcs[q].op == QA_OP_US ? 2 : 1;
+                    for (int z = 0; z < w; ++z) busy[slot_of[q] + z] = 0;
+                }
+                slot_of[pi] = grab(pc.op == QA_OP_US ? 2 : 1);
+                dp.out_slot = slot_of[pi];
+                for (int z = 0; z < QA_MAXPOLY; ++z) if (busy[z]) npoly_max = std::max(npoly_max, z + 1);
+                const auto& tv = T.tabs[ti][pi];
+                dp.ntab = (int)tv.size();
+                uint64_t taboff = P.alloc(sizeof(DevTable) * tv.size(), 64);
+                dp.tab_off = taboff;
+                std::memcpy(P.buf.data() + poff + pi * sizeof(DevPiece), &dp, sizeof dp);
+                for (size_t k = 0; k < tv.size(); ++k) {
+                    const Table& tb = tv[k];
+                    uint64_t hoff = P.alloc(sizeof(DevBlock) * std::max<size_t>(1, tb.blocks.size()), 64);
+                    size_t ncoef = 0;
+                    for (auto& b : tb.blocks) ncoef += b.coef.size();
+                    uint64_t coff = P.alloc(8 * std::max<size_t>(1, ncoef), 256);
+                    DevTable dtb{};
+                    dtb.nblocks = (int)tb.blocks.size();
+                    dtb.has_q = tb.has_q;
+                    dtb.scale = tb.scale;
+                    dtb.hdr_off = hoff;
+                    dtb.coef_off = coff;
+                    std::memcpy(P.buf.data() + taboff + k * sizeof(DevTable), &dtb, sizeof dtb);
+                    size_t c = 0;
+                    for (size_t bi = 0; bi < tb.blocks.size(); ++bi) {
+                        const Block& b = tb.blocks[bi];
+                        DevBlock db{};
+                        db.k = (uint8_t)b.k; db.r = (uint8_t)b.r; db.coef = (uint32_t)c;
+                        std::memcpy(db.bidx, b.bidx, QA_MAXK);
+                        std::memcpy(db.aidx, b.aidx, QA_MAXR);
+                        std::memcpy(db.cidx, b.cidx, QA_MAXR);
+                        std::memcpy(P.buf.data() + hoff + bi * sizeof(DevBlock), &db, sizeof db);
+                        std::memcpy(P.buf.data() + coff + 8 * c, b.coef.data(), 8 * b.coef.size());
+                        c += b.coef.size();
+                    }
+                }
+            }
+        }
+        DevGraph dg{};
+        dg.n = T.g.n; dg.M = M; dg.mult = T.g.mult; dg.nterms = (int)T.terms.size();
+        dg.deg_off = doff; dg.w_off = woff; dg.terms_off = toff; dg.npoly = std::max(1, npoly_max);
+        std::memcpy(P.buf.data() + goff + gi * sizeof(DevGraph), &dg, sizeof dg);
+    }
+    out.swap(P.buf);
+    return QA_OK;
+}
+
+// image cache: the packed bytes for (set, pdf)
+static std::mutex g_pack_mu;
+static std::map<std::pair<const void*, const void*>, std::vector<uint8_t>> g_images;
+
+const std::vector<uint8_t>* qa_image(const qa_set* s, const qa_pdf* p) {
+    std::lock_guard<std::mutex> l(g_pack_mu);
+    auto key = std::make_pair((const void*)s, (const void*)p);
+    auto it = g_images.find(key);
+    if (it != g_images.end()) return &it->second;
+    std::vector<uint8_t> img;
+    if (pack(s, p, img) != QA_OK) return nullptr;
+    return &(g_images[key] = std::move(img));
+}
+
+void qa_image_forget(const void* s, const void* p) {
+    std::lock_guard<std::mutex> l(g_pack_mu);
+    for (auto it = g_images.begin(); it != g_images.end();) {
+        if (it->first.first == s || it->first.second == p) it = g_images.erase(it); else ++it;
+    }
+}
+
+extern "C" int qa_device_bytes(const qa_set* s, const qa_pdf* p, size_t* bytes) {
+    try {
+        if (!bytes) return fail(QA_EINVAL, "NULL bytes");
+        auto* img = qa_image(s, p);
+        if (!img) return QA_EINVAL;
+        *bytes = img->size();
+        return QA_OK;
+    } catch (std::exception& e) { return fail(QA_EINVAL, e.what()); }
+}
+
+extern "C" int qa_dirac_trace(const int32_t* sym, int len, double* out) {
+    try {
+        if (!sym || !out || len < 0 || len > 60) return fail(QA_EINVAL, "bad string");
+        *out = (double)dirac_trace(sym, len);
+        return QA_OK;
+    } catch (std::exception& e) { return fail(QA_EINVAL, e.what()); }
+}
+
+// graph / pdf accessors for the launch code
+const GraphTables& qa_graph_tables(const qa_set* s, size_t i) { return s->graphs[i]; }
+size_t qa_set_size(const qa_set* s) { return s->graphs.size(); }

@@ -1,0 +1,718 @@
+// HIP kernels of the hot path (gfx950) and the C-ABI entry points that launch them.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qedamm.h"
+#include "eval.h"
+#include "host.h"
+
+const std::vector<uint8_t>* qa_image(const qa_set* s, const qa_pdf* p);
+int qa_fail(int code, const std::string& msg);
+size_t qa_set_size(const qa_set* s);
+const qa::GraphTables& qa_graph_tables(const qa_set* s, size_t i);
+
+#define HIPCHK(x)                                                                  \
+    do {                                                                           \
+        hipError_t e_ = (x);                                                       \
+        if (e_ != hipSuccess) return qa_fail(QA_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al. 2011) and the uniform double mapping
+
+__device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ double u01(uint32_t a, uint32_t b) {
+    const uint64_t k = (uint64_t)(a >> 6) * 67108864ull + (b >> 6);
+    return (double)(2 * k + 1) * 0x1p-53;
+}
+
+struct Stream {
+    uint2 key;
+    uint32_t graph;
+    uint64_t sample;
+    __device__ void pair(int blk, double& u0, double& u1) const {
+        uint4 x = philox(make_uint4((uint32_t)blk, graph, (uint32_t)sample, (uint32_t)(sample >> 32)), key);
+        u0 = u01(x.x, x.y);
+        u1 = u01(x.z, x.w);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// sector-tree sampling from eq. (1): choose j_1..j_M with P(j | S) =
+// W(S\j) / sum_j' W(S\j'), then t_l ~ Exp(Deg(S_l)) and ln z_{j_l} = -sum t.
+// Writes z (normalised) through zv, returns log p; order[l] = j_(l+1).
+__device__ bool sample_point(const double* __restrict__ D, const double* __restrict__ W, int M, const Stream& st,
+                             LV<double> zv, double& logp, uint8_t* order, double* tl) {
+    const uint32_t full = (1u << M) - 1;
+    uint32_t S = full;
+    double u0 = 0.0, u1 = 0.0;
+    int ublk = -1;
+    auto uni = [&](int i) {
+        if ((i >> 1) != ublk) { ublk = i >> 1; st.pair(ublk, u0, u1); }
+        return (i & 1) ? u1 : u0;
+    };
+#pragma unroll
+    for (int l = 0; l < QA_MAXM - 1; ++l) {
+        if (l >= M - 1) break;
+        double ws[QA_MAXM];
+        double tot = 0.0;
+#pragma unroll
+        for (int j = 0; j < QA_MAXM; ++j) {
+            ws[j] = 0.0;
+            if (j < M && (S >> j & 1)) { ws[j] = W[S ^ (1u << j)]; tot += ws[j]; }
+        }
+        const double target = uni(l) * tot;
+        double cum = 0.0;
+        int pick = -1, last = 0;
+#pragma unroll
+        for (int j = 0; j < QA_MAXM; ++j) {
+            if (j < M && (S >> j & 1)) {
+                last = j;
+                if (pick < 0) {
+                    cum += ws[j];
+                    if (target < cum) pick = j;
+                }
+            }
+        }
+        if (pick < 0) pick = last;
+        order[l] = (uint8_t)pick;
+        S ^= 1u << pick;
+    }
+    order[M - 1] = (uint8_t)__builtin_ctz(S);
+    S = full ^ (1u << order[0]);
+    double run = 0.0, degsum = 0.0, lzsum = 0.0;
+    zv[order[0]] = 0.0;
+#pragma unroll
+    for (int l = 1; l < QA_MAXM; ++l) {
+        if (l >= M) break;
+        const double d = D[S];
+        const double t = -log(uni(M - 1 + l - 1)) / d;
+        tl[l] = t;
+        run -= t;
+        degsum += d * t;
+        lzsum += run;
+        zv[order[l]] = run;
+        S ^= 1u << order[l];
+    }
+    double norm = 0.0;
+    for (int i = 0; i < M; ++i) { const double e = exp(zv[i]); zv[i] = e; norm += e; }
+    const double inv = 1.0 / norm;
+    bool ok = true;
+    for (int i = 0; i < M; ++i) { zv[i] *= inv; ok &= zv[i] > 0.0; }
+    logp = -log(W[full]) - degsum - (lzsum - M * log(norm));
+    return ok && isfinite(logp);
+}
+
+__device__ __forceinline__ const DevGraph& dev_graph(const uint8_t* img, uint32_t g) {
+    const DevHeader* h = reinterpret_cast<const DevHeader*>(img);
+    return reinterpret_cast<const DevGraph*>(img + h->graphs_off)[g];
+}
+
+__global__ void __launch_bounds__(256) k_sample(const uint8_t* __restrict__ img, uint32_t graph, uint2 key,
+                                                uint64_t first, uint64_t count, double* __restrict__ z,
+                                                double* __restrict__ logp, uint8_t* __restrict__ sector) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const DevGraph& G = dev_graph(img, graph);
+    const double* D = reinterpret_cast<const double*>(img + G.deg_off);
+    const double* W = reinterpret_cast<const double*>(img + G.w_off);
+    Stream st{key, graph, first + i};
+    uint8_t order[QA_MAXM];
+    double tl[QA_MAXM];
+    double lp;
+    sample_point(D, W, G.M, st, LV<double>{z + i, (int)count}, lp, order, tl);
+    logp[i] = lp;
+    if (sector)
+        for (int l = 0; l < G.M; ++l) sector[(uint64_t)l * count + i] = order[l];
+}
+
+// ---------------------------------------------------------------------------
+// evaluation kernels: one point per lane, per-lane scratch in LDS laid out
+// [element][lane]: geometry variables (QA_NVAR of the geometry type) then the
+// piece-result polynomials (npoly * QA_MAXN of the evaluation type).
+
+template <class T> __device__ __forceinline__ void lane_views(char* lds, int npoly, LV<typename GeoOf<T>::type>& vars,
+                                                             LV<T>& polys) {
+    using S = typename GeoOf<T>::type;
+    const int lane = threadIdx.x, nt = blockDim.x;
+    S* vbase = reinterpret_cast<S*>(lds);
+    T* pbase = reinterpret_cast<T*>(lds + sizeof(S) * QA_NVAR * nt);
+    vars = LV<S>{vbase + lane, nt};
+    polys = LV<T>{pbase + lane, nt};
+    (void)npoly;
+}
+
+template <class T> __host__ __device__ size_t lds_bytes_dev(int npoly, int nt) {
+    using S = typename GeoOf<T>::type;
+    return (sizeof(S) * QA_NVAR + sizeof(T) * QA_MAXN * npoly) * nt;
+}
+template <class T> size_t lds_bytes(int npoly, int nt) { return lds_bytes_dev<T>(npoly, nt); }
+
+constexpr double QA_U = 0x1p-53;
+__device__ __forceinline__ double bound_of(double mag, double cond) { return mag * QA_U * (64.0 + 12.0 * cond); }
+
+__global__ void __launch_bounds__(64) k_eval_fp64(const uint8_t* __restrict__ img, uint32_t graph,
+                                                  const double* __restrict__ z, uint64_t count, double* __restrict__ f) {
+    extern __shared__ char lds[];
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const DevGraph& G = dev_graph(img, graph);
+    LV<double> vars, polys;
+    lane_views<double>(lds, G.npoly, vars, polys);
+    double cond;
+    f[i] = eval_point<double>(img, G, CLV<double>{z + i, (int)count}, vars, polys, cond);
+}
+
+__global__ void __launch_bounds__(64) k_eval_bound(const uint8_t* __restrict__ img, uint32_t graph,
+                                                   const double* __restrict__ z, uint64_t count, double* __restrict__ f,
+                                                   double* __restrict__ err, uint8_t* __restrict__ flag) {
+    extern __shared__ char lds[];
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const DevGraph& G = dev_graph(img, graph);
+    LV<double> vars;
+    LV<EB> polys;
+    lane_views<EB>(lds, G.npoly, vars, polys);
+    double cond;
+    EB r = eval_point<EB>(img, G, CLV<double>{z + i, (int)count}, vars, polys, cond);
+    const double e = bound_of(r.a, cond);
+    f[i] = r.v;
+    if (err) err[i] = e;
+    if (flag) flag[i] = !(e <= 1e-11 * fabs(r.v));
+}
+
+__global__ void __launch_bounds__(64) k_eval_dd(const uint8_t* __restrict__ img, uint32_t graph,
+                                                const double* __restrict__ z, uint64_t count, double* __restrict__ f,
+                                                double* __restrict__ err) {
+    extern __shared__ char lds[];
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const DevGraph& G = dev_graph(img, graph);
+    LV<DD> vars, polys;
+    lane_views<DD>(lds, G.npoly, vars, polys);
+    double cond;
+    DD r = eval_point<DD>(img, G, CLV<double>{z + i, (int)count}, vars, polys, cond);
+    f[i] = r.hi + r.lo;
+    if (err) err[i] = fabs(r.hi) * 0x1p-100 * (64.0 + 12.0 * cond * cond) + fabs(r.lo) * 0x1p-53;
+}
+
+// ---------------------------------------------------------------------------
+// compensated sums
+
+__device__ __forceinline__ DD dd_add(DD a, DD b) { return a + b; }
+
+__device__ DD wave_sum_dd(DD v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        DD o{__shfl_xor(v.hi, off), __shfl_xor(v.lo, off)};
+        v = v + o;
+    }
+    return v;
+}
+__device__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// single block, fixed order: deterministic for a given count
+__global__ void __launch_bounds__(1024) k_accumulate(const double* __restrict__ f, const double* __restrict__ logp,
+                                                     uint64_t count, qa_acc* acc) {
+    __shared__ double sh[4][16];
+    __shared__ uint64_t sn[2][16];
+    DD s1{0, 0}, s2{0, 0};
+    uint64_t n = 0, bad = 0;
+    for (uint64_t i = threadIdx.x; i < count; i += blockDim.x) {
+        const double w = f[i] * exp(-logp[i]);
+        if (!isfinite(w)) { ++bad; continue; }
+        s1 = s1 + dd(w);
+        s2 = s2 + two_prod(w, w);
+        ++n;
+    }
+    s1 = wave_sum_dd(s1);
+    s2 = wave_sum_dd(s2);
+    n = wave_sum_u64(n);
+    bad = wave_sum_u64(bad);
+    const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+    if (ln == 0) { sh[0][wv] = s1.hi; sh[1][wv] = s1.lo; sh[2][wv] = s2.hi; sh[3][wv] = s2.lo; sn[0][wv] = n; sn[1][wv] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DD a1{acc->s1_hi, acc->s1_lo}, a2{acc->s2_hi, acc->s2_lo};
+        uint64_t an = acc->n, ab = acc->n_bad;
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) {
+            a1 = a1 + DD{sh[0][w], sh[1][w]};
+            a2 = a2 + DD{sh[2][w], sh[3][w]};
+            an += sn[0][w];
+            ab += sn[1][w];
+        }
+        acc->s1_hi = a1.hi; acc->s1_lo = a1.lo;
+        acc->s2_hi = a2.hi; acc->s2_lo = a2.lo;
+        acc->n = an;
+        acc->n_bad = ab;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// batched form: persistent waves over tiles (graph, sample range)
+
+struct Partial {
+    double s1_hi, s1_lo, s2_hi, s2_lo;
+    uint64_t n, nflag, nbad, pad;
+};
+struct FlagEntry {
+    uint64_t sample;
+    double w;         // FP64 weight
+    double c1, c2;    // corrections written by the double-double pass
+};
+struct Work {
+    uint32_t* counter;       // [0] tile queue, [1] round
+    uint64_t* gtile0;        // per graph: first global tile index (ng + 1 entries)
+    uint64_t* budget;        // per graph samples
+    Partial* partial;        // per round-tile
+    uint32_t* nflag;         // per round-tile
+    FlagEntry* flags;        // per round-tile * tile
+    double* zbuf;            // per persistent wave: QA_MAXM * 64
+    uint32_t tile, per_round, ng;
+    uint64_t ntiles;
+};
+
+__device__ __forceinline__ void tile_of(const Work& w, uint64_t gt, uint32_t& g, uint64_t& s0, uint32_t& cnt) {
+    uint32_t lo = 0, hi = w.ng;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) / 2;
+        if (w.gtile0[mid] <= gt) lo = mid; else hi = mid;
+    }
+    g = lo;
+    s0 = (gt - w.gtile0[lo]) * w.tile;
+    const uint64_t rem = w.budget[lo] - s0;
+    cnt = (uint32_t)(rem < w.tile ? rem : w.tile);
+}
+
+__global__ void k_reset(Work w) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) w.counter[0] = 0;
+}
+__global__ void k_next_round(Work w) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) w.counter[1] += 1;
+}
+
+__global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, uint2 key, Work w) {
+    extern __shared__ char lds[];
+    const int lane = threadIdx.x;
+    LV<double> vars;
+    LV<EB> polys;
+    lane_views<EB>(lds, 0, vars, polys);
+    double* zb = w.zbuf + (uint64_t)blockIdx.x * QA_MAXM * 64;
+    const uint64_t round = w.counter[1];
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(w.counter, 1u);
+        t = __shfl(t, 0);
+        if (t >= w.per_round) break;
+        const uint64_t gt = round * w.per_round + t;
+        Partial pr{};
+        if (gt >= w.ntiles) {
+            if (lane == 0) { w.partial[t] = pr; w.nflag[t] = 0; }
+            continue;
+        }
+        uint32_t g, cnt;
+        uint64_t s0;
+        tile_of(w, gt, g, s0, cnt);
+        const DevGraph& G = dev_graph(img, g);
+        const double* D = reinterpret_cast<const double*>(img + G.deg_off);
+        const double* W = reinterpret_cast<const double*>(img + G.w_off);
+        DD s1{0, 0}, s2{0, 0};
+        uint64_t n = 0, bad = 0;
+        uint32_t nfl = 0;
+        for (uint32_t base = 0; base < cnt; base += 64) {
+            const uint32_t j = base + lane;
+            const bool act = j < cnt;
+            double wv = 0.0;
+            bool flagged = false, good = false;
+            if (act) {
+                Stream st{key, g, s0 + j};
+                uint8_t order[QA_MAXM];
+                double tl[QA_MAXM];
+                double lp;
+                LV<double> zv{zb + lane, 64};
+                bool ok = sample_point(D, W, G.M, st, zv, lp, order, tl);
+                if (ok) {
+                    double cond;
+                    EB r = eval_point<EB>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond);
+                    const double e = bound_of(r.a, cond);
+                    wv = r.v * exp(-lp);
+                    good = isfinite(wv);
+                    flagged = good && !(e <= 1e-11 * fabs(r.v));
+                }
+            }
+            if (act && good) {
+                s1 = s1 + dd(wv);
+                s2 = s2 + two_prod(wv, wv);
+                ++n;
+            } else if (act) {
+                ++bad;
+            }
+            const uint64_t mask = __ballot(flagged);
+            if (flagged) {
+                const uint32_t pos = nfl + __popcll(mask & ((1ull << lane) - 1));
+                FlagEntry& fe = w.flags[(uint64_t)t * w.tile + pos];
+                fe.sample = s0 + j;
+                fe.w = wv;
+                fe.c1 = 0.0;
+                fe.c2 = 0.0;
+            }
+            nfl += __popcll(mask);
+        }
+        s1 = wave_sum_dd(s1);
+        s2 = wave_sum_dd(s2);
+        n = wave_sum_u64(n);
+        bad = wave_sum_u64(bad);
+        if (lane == 0) {
+            pr.s1_hi = s1.hi; pr.s1_lo = s1.lo; pr.s2_hi = s2.hi; pr.s2_lo = s2.lo;
+            pr.n = n; pr.nflag = nfl; pr.nbad = bad;
+            w.partial[t] = pr;
+            w.nflag[t] = nfl;
+        }
+    }
+}
+
+// double-double recompute of the flagged points of this round
+__global__ void __launch_bounds__(64) k_fix_dd(const uint8_t* __restrict__ img, uint2 key, Work w) {
+    extern __shared__ char lds[];
+    const int lane = threadIdx.x;
+    LV<DD> vars, polys;
+    lane_views<DD>(lds, 0, vars, polys);
+    double* zb = w.zbuf + (uint64_t)blockIdx.x * QA_MAXM * 64;
+    const uint64_t round = w.counter[1];
+    for (uint32_t t = blockIdx.x; t < w.per_round; t += gridDim.x) {
+        const uint32_t nf = w.nflag[t];
+        if (nf == 0) continue;
+        const uint64_t gt = round * w.per_round + t;
+        uint32_t g, cnt;
+        uint64_t s0;
+        tile_of(w, gt, g, s0, cnt);
+        const DevGraph& G = dev_graph(img, g);
+        const double* D = reinterpret_cast<const double*>(img + G.deg_off);
+        const double* W = reinterpret_cast<const double*>(img + G.w_off);
+        for (uint32_t b = 0; b < nf; b += 64) {
+            const uint32_t e = b + lane;
+            if (e >= nf) continue;
+            FlagEntry& fe = w.flags[(uint64_t)t * w.tile + e];
+            Stream st{key, g, fe.sample};
+            uint8_t order[QA_MAXM];
+            double tl[QA_MAXM], lp, cond;
+            LV<double> zv{zb + lane, 64};
+            sample_point(D, W, G.M, st, zv, lp, order, tl);
+            DD r = eval_point<DD>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond);
+            const DD wd = r * exp(-lp);
+            const DD d1 = wd - dd(fe.w);
+            const DD d2 = wd * wd - two_prod(fe.w, fe.w);
+            fe.c1 = d1.hi + d1.lo;
+            fe.c2 = d2.hi + d2.lo;
+        }
+    }
+}
+
+// per graph, in tile order: partials then corrections -> acc
+__global__ void k_reduce(Work w, qa_acc* acc) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= w.ng) return;
+    const uint64_t round = w.counter[1];
+    const uint64_t t0 = round * w.per_round, t1 = t0 + w.per_round;
+    const uint64_t a = w.gtile0[g] > t0 ? w.gtile0[g] : t0;
+    const uint64_t b = w.gtile0[g + 1] < t1 ? w.gtile0[g + 1] : t1;
+    if (a >= b) return;
+    DD s1{acc[g].s1_hi, acc[g].s1_lo}, s2{acc[g].s2_hi, acc[g].s2_lo};
+    uint64_t n = acc[g].n, nf = acc[g].n_flagged, nb = acc[g].n_bad;
+    for (uint64_t gt = a; gt < b; ++gt) {
+        const uint32_t t = (uint32_t)(gt - t0);
+        const Partial& p = w.partial[t];
+        s1 = s1 + DD{p.s1_hi, p.s1_lo};
+        s2 = s2 + DD{p.s2_hi, p.s2_lo};
+        n += p.n;
+        nb += p.nbad;
+        for (uint32_t e = 0; e < w.nflag[t]; ++e) {
+            const FlagEntry& fe = w.flags[(uint64_t)t * w.tile + e];
+            s1 = s1 + dd(fe.c1);
+            s2 = s2 + dd(fe.c2);
+        }
+        nf += w.nflag[t];
+    }
+    acc[g].s1_hi = s1.hi; acc[g].s1_lo = s1.lo;
+    acc[g].s2_hi = s2.hi; acc[g].s2_lo = s2.lo;
+    acc[g].n = n; acc[g].n_flagged = nf; acc[g].n_bad = nb;
+}
+
+// ---------------------------------------------------------------------------
+// variance gradient: grad[S_l] += w^2 t_l, w2sum += w^2
+
+__global__ void __launch_bounds__(64) k_vargrad(const uint8_t* __restrict__ img, uint32_t graph, uint2 key,
+                                                uint64_t first, uint64_t count, double* grad, double* w2sum) {
+    extern __shared__ char lds[];
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const DevGraph& G = dev_graph(img, graph);
+    LV<double> vars, polys;
+    lane_views<double>(lds, G.npoly, vars, polys);
+    // z after the polynomial region
+    double* zb = reinterpret_cast<double*>(lds + lds_bytes_dev<double>(G.npoly, blockDim.x));
+    double w2 = 0.0;
+    if (i < count) {
+        const double* D = reinterpret_cast<const double*>(img + G.deg_off);
+        const double* W = reinterpret_cast<const double*>(img + G.w_off);
+        Stream st{key, graph, first + i};
+        uint8_t order[QA_MAXM];
+        double tl[QA_MAXM], lp, cond;
+        LV<double> zv{zb + threadIdx.x, (int)blockDim.x};
+        if (sample_point(D, W, G.M, st, zv, lp, order, tl)) {
+            const double f = eval_point<double>(img, G, CLV<double>{zb + threadIdx.x, (int)blockDim.x}, vars, polys, cond);
+            const double w = f * exp(-lp);
+            if (isfinite(w)) {
+                w2 = w * w;
+                uint32_t S = (1u << G.M) - 1;
+                for (int l = 1; l < G.M; ++l) {
+                    S ^= 1u << order[l - 1];
+                    atomicAdd(grad + S, w2 * tl[l]);
+                }
+            }
+        }
+    }
+    // one atomic per wave for the w^2 sum
+    double s = w2;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) atomicAdd(w2sum, s);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI launchers
+
+// allow more than the default 64 KB of dynamic LDS where a launch needs it
+template <class K> static int lds_attr(K kernel, size_t bytes) {
+    if (bytes > 160 * 1024) return qa_fail(QA_ENOTSUP, "LDS requirement exceeds 160 KB");
+    if (bytes > 64 * 1024)
+        HIPCHK(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return QA_OK;
+}
+
+static const DevGraph* host_graph(const std::vector<uint8_t>& img, uint32_t g) {
+    const DevHeader* h = reinterpret_cast<const DevHeader*>(img.data());
+    if (g >= h->ngraphs) return nullptr;
+    return reinterpret_cast<const DevGraph*>(img.data() + h->graphs_off) + g;
+}
+
+// the host copy of the last image uploaded to each device buffer
+#include <map>
+#include <mutex>
+static std::mutex g_up_mu;
+static std::map<const void*, const std::vector<uint8_t>*> g_uploaded;
+
+static const std::vector<uint8_t>* image_of(const void* dev) {
+    std::lock_guard<std::mutex> l(g_up_mu);
+    auto it = g_uploaded.find(dev);
+    return it == g_uploaded.end() ? nullptr : it->second;
+}
+
+extern "C" int qa_upload(const qa_set* s, const qa_pdf* p, void* dev, size_t bytes, void* stream) {
+    auto* img = qa_image(s, p);
+    if (!img) return QA_EINVAL;
+    if (!dev || bytes < img->size()) return qa_fail(QA_ECAP, "device buffer too small");
+    HIPCHK(hipMemcpyAsync(dev, img->data(), img->size(), hipMemcpyHostToDevice, (hipStream_t)stream));
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    std::lock_guard<std::mutex> l(g_up_mu);
+    g_uploaded[dev] = img;
+    return QA_OK;
+}
+
+extern "C" int qa_sample_pdf(const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, uint64_t first,
+                             uint64_t count, double* z, double* logp, uint8_t* sector, void* stream) {
+    auto* img = image_of(dev);
+    if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
+    if (!host_graph(*img, graph)) return qa_fail(QA_EINVAL, "graph index out of range");
+    if (!z || !logp) return qa_fail(QA_EINVAL, "NULL output");
+    if (count == 0) return QA_OK;
+    if (count > (1ull << 31)) return qa_fail(QA_EINVAL, "count too large for one call");
+    const uint2 key = make_uint2((uint32_t)seed, tag);
+    dim3 grid((unsigned)((count + 255) / 256));
+    hipLaunchKernelGGL(k_sample, grid, dim3(256), 0, (hipStream_t)stream, (const uint8_t*)dev, graph, key, first,
+                       count, z, logp, sector);
+    HIPCHK(hipGetLastError());
+    return QA_OK;
+}
+
+extern "C" int qa_eval_integrand(const void* dev, uint32_t graph, const double* z, uint64_t count, int mode, double* f,
+                                 double* err, uint8_t* flag, void* stream) {
+    auto* img = image_of(dev);
+    if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
+    const DevGraph* G = host_graph(*img, graph);
+    if (!G) return qa_fail(QA_EINVAL, "graph index out of range");
+    if (!z || !f) return qa_fail(QA_EINVAL, "NULL argument");
+    if (count == 0) return QA_OK;
+    if (count > (1ull << 31)) return qa_fail(QA_EINVAL, "count too large for one call");
+    dim3 grid((unsigned)((count + 63) / 64)), block(64);
+    const uint8_t* d = (const uint8_t*)dev;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = QA_OK;
+    if (mode == QA_FP64) rc = lds_attr(k_eval_fp64, lds_bytes<double>(G->npoly, 64));
+    else if (mode == QA_FP64_BOUND) rc = lds_attr(k_eval_bound, lds_bytes<EB>(G->npoly, 64));
+    else if (mode == QA_DD) rc = lds_attr(k_eval_dd, lds_bytes<DD>(G->npoly, 64));
+    if (rc != QA_OK) return rc;
+    if (mode == QA_FP64) {
+        hipLaunchKernelGGL(k_eval_fp64, grid, block, lds_bytes<double>(G->npoly, 64), st, d, graph, z, count, f);
+    } else if (mode == QA_FP64_BOUND) {
+        hipLaunchKernelGGL(k_eval_bound, grid, block, lds_bytes<EB>(G->npoly, 64), st, d, graph, z, count, f, err, flag);
+    } else if (mode == QA_DD) {
+        hipLaunchKernelGGL(k_eval_dd, grid, block, lds_bytes<DD>(G->npoly, 64), st, d, graph, z, count, f, err);
+    } else {
+        return qa_fail(QA_EINVAL, "bad mode");
+    }
+    HIPCHK(hipGetLastError());
+    return QA_OK;
+}
+
+extern "C" int qa_accumulate(const double* f, const double* logp, uint64_t count, qa_acc* acc, void* stream) {
+    if (!f || !logp || !acc) return qa_fail(QA_EINVAL, "NULL argument");
+    if (count == 0) return QA_OK;
+    hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(1024), 0, (hipStream_t)stream, f, logp, count, acc);
+    HIPCHK(hipGetLastError());
+    return QA_OK;
+}
+
+// work buffer layout for qa_integrate
+struct WorkLayout {
+    size_t counter, gtile0, budget, partial, nflag, flags, zbuf, total;
+};
+static WorkLayout work_layout(size_t ng, uint32_t tile, uint32_t per_round, uint32_t grid) {
+    WorkLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = (o + bytes + 255) / 256 * 256; return r; };
+    L.counter = take(16);
+    L.gtile0 = take(8 * (ng + 1));
+    L.budget = take(8 * ng);
+    L.partial = take(sizeof(Partial) * per_round);
+    L.nflag = take(4 * per_round);
+    L.flags = take(sizeof(FlagEntry) * (size_t)per_round * tile);
+    L.zbuf = take(8ull * QA_MAXM * 64 * grid);
+    L.total = o;
+    return L;
+}
+
+static const uint32_t kPerRound = 2048;
+
+static uint32_t default_grid() {
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+    }
+    return (uint32_t)ncu * 4;
+}
+
+extern "C" int qa_work_bytes(const qa_set* s, const uint64_t* budgets, uint32_t tile, size_t* bytes) {
+    if (!s || !bytes) return qa_fail(QA_EINVAL, "NULL argument");
+    (void)budgets;
+    if (tile == 0) tile = 1024;
+    if (tile % 64) return qa_fail(QA_EINVAL, "tile must be a multiple of 64");
+    // enough persistent waves for any grid up to 8 per CU on 256 CUs
+    *bytes = work_layout(qa_set_size(s), tile, kPerRound, 2048).total;
+    return QA_OK;
+}
+
+extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t seed, uint32_t tag,
+                            uint32_t tile, uint32_t grid, void* work, size_t work_bytes, qa_acc* acc, void* stream) {
+    auto* img = image_of(dev);
+    if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
+    if (!s || !budgets || !work || !acc) return qa_fail(QA_EINVAL, "NULL argument");
+    const size_t ng = qa_set_size(s);
+    if (reinterpret_cast<const DevHeader*>(img->data())->ngraphs != ng) return qa_fail(QA_EINVAL, "set / image mismatch");
+    if (tile == 0) tile = 1024;
+    if (tile % 64) return qa_fail(QA_EINVAL, "tile must be a multiple of 64");
+    if (grid == 0) grid = default_grid();
+    if (grid > 2048) return qa_fail(QA_EINVAL, "grid too large (max 2048 waves)");
+    WorkLayout L = work_layout(ng, tile, kPerRound, grid);
+    if (work_bytes < L.total) return qa_fail(QA_ECAP, "work buffer too small");
+    std::vector<uint64_t> g0(ng + 1, 0);
+    for (size_t g = 0; g < ng; ++g) g0[g + 1] = g0[g] + (budgets[g] + tile - 1) / tile;
+    const uint64_t ntiles = g0[ng];
+    hipStream_t st = (hipStream_t)stream;
+    char* wb = (char*)work;
+    uint32_t zero[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(wb + L.counter, zero, 16, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(wb + L.gtile0, g0.data(), 8 * (ng + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(wb + L.budget, budgets, 8 * ng, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(acc, 0, sizeof(qa_acc) * ng, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (ntiles == 0) return QA_OK;
+    Work w{};
+    w.counter = (uint32_t*)(wb + L.counter);
+    w.gtile0 = (uint64_t*)(wb + L.gtile0);
+    w.budget = (uint64_t*)(wb + L.budget);
+    w.partial = (Partial*)(wb + L.partial);
+    w.nflag = (uint32_t*)(wb + L.nflag);
+    w.flags = (FlagEntry*)(wb + L.flags);
+    w.zbuf = (double*)(wb + L.zbuf);
+    w.tile = tile;
+    w.per_round = kPerRound;
+    w.ng = (uint32_t)ng;
+    w.ntiles = ntiles;
+    const uint2 key = make_uint2((uint32_t)seed, tag);
+    int maxpoly = 1;
+    for (size_t g = 0; g < ng; ++g) maxpoly = std::max(maxpoly, host_graph(*img, (uint32_t)g)->npoly);
+    const size_t lds_fp = lds_bytes<EB>(maxpoly, 64), lds_dd = lds_bytes<DD>(maxpoly, 64);
+    const uint64_t rounds = (ntiles + kPerRound - 1) / kPerRound;
+    if (int rc = lds_attr(k_fused, lds_fp)) return rc;
+    if (int rc = lds_attr(k_fix_dd, lds_dd)) return rc;
+    // one round as a graph: reset queue, fused pass, double-double pass, reduce, advance
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, w);
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(64), lds_fp, st, (const uint8_t*)dev, key, w);
+    hipLaunchKernelGGL(k_fix_dd, dim3(grid), dim3(64), lds_dd, st, (const uint8_t*)dev, key, w);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, st, w, acc);
+    hipLaunchKernelGGL(k_next_round, dim3(1), dim3(64), 0, st, w);
+    HIPCHK(hipStreamEndCapture(st, &graph));
+    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    for (uint64_t r = 0; r < rounds; ++r) {
+        hipError_t e = hipGraphLaunch(exec, st);
+        if (e != hipSuccess) {
+            hipGraphExecDestroy(exec);
+            hipGraphDestroy(graph);
+            return qa_fail(QA_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGraphExecDestroy(exec));
+    HIPCHK(hipGraphDestroy(graph));
+    return QA_OK;
+}
+
+extern "C" int qa_variance_grad(const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, uint64_t first,
+                                uint64_t count, double* grad, double* w2sum, void* stream) {
+    auto* img = image_of(dev);
+    if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
+    const DevGraph* G = host_graph(*img, graph);
+    if (!G) return qa_fail(QA_EINVAL, "graph index out of range");
+    if (!grad || !w2sum) return qa_fail(QA_EINVAL, "NULL argument");
+    if (count == 0) return QA_OK;
+    if (count > (1ull << 31)) return qa_fail(QA_EINVAL, "count too large for one call");
+    const unsigned nb = (unsigned)((count + 63) / 64);
+    if (int rc = lds_attr(k_vargrad, lds_bytes<double>(G->npoly, 64) + 8 * QA_MAXM * 64)) return rc;
+    hipLaunchKernelGGL(k_vargrad, dim3(nb), dim3(64), lds_bytes<double>(G->npoly, 64) + 8 * QA_MAXM * 64,
+                       (hipStream_t)stream, (const uint8_t*)dev, graph, make_uint2((uint32_t)seed, tag), first, count,
+                       grad, w2sum);
+    HIPCHK(hipGetLastError());
+    return QA_OK;
+}

@@ -1,0 +1,104 @@
+// Number types of the integrand evaluator: plain double, double with a
+// running magnitude (for the error bound), and double-double.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#define QA_HD __host__ __device__ __forceinline__
+
+// ---- value + magnitude: every operation also propagates |.| so that the
+// final magnitude bounds the rounding error of the value (a priori bound).
+struct EB {
+    double v, a;
+};
+QA_HD EB eb(double x) { return EB{x, fabs(x)}; }
+QA_HD EB operator+(EB x, EB y) { return EB{x.v + y.v, x.a + y.a}; }
+QA_HD EB operator-(EB x, EB y) { return EB{x.v - y.v, x.a + y.a}; }
+QA_HD EB operator*(EB x, EB y) { return EB{x.v * y.v, x.a * y.a}; }
+QA_HD EB operator*(EB x, double c) { return EB{x.v * c, x.a * fabs(c)}; }
+QA_HD EB& operator+=(EB& x, EB y) { x = x + y; return x; }
+QA_HD EB& operator*=(EB& x, EB y) { x = x * y; return x; }
+QA_HD EB operator/(EB x, EB y) { return EB{x.v / y.v, x.a / fabs(y.v)}; }
+QA_HD EB operator-(EB x) { return EB{-x.v, x.a}; }
+QA_HD EB fma_(EB a, EB b, EB c) { return EB{fma(a.v, b.v, c.v), a.a * b.a + c.a}; }
+QA_HD double val(EB x) { return x.v; }
+QA_HD double mag(EB x) { return x.a; }
+
+QA_HD double fma_(double a, double b, double c) { return fma(a, b, c); }
+QA_HD double val(double x) { return x; }
+QA_HD double mag(double x) { return fabs(x); }
+
+// ---- double-double (Dekker / Knuth error-free transformations)
+struct DD {
+    double hi, lo;
+};
+QA_HD DD two_sum(double a, double b) {
+    double s = a + b;
+    double bb = s - a;
+    double e = (a - (s - bb)) + (b - bb);
+    return DD{s, e};
+}
+QA_HD DD quick_two_sum(double a, double b) {
+    double s = a + b;
+    double e = b - (s - a);
+    return DD{s, e};
+}
+QA_HD DD two_prod(double a, double b) {
+    double p = a * b;
+    double e = fma(a, b, -p);
+    return DD{p, e};
+}
+QA_HD DD dd(double x) { return DD{x, 0.0}; }
+QA_HD DD operator+(DD a, DD b) {
+    DD s = two_sum(a.hi, b.hi);
+    DD t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = quick_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return quick_two_sum(s.hi, s.lo);
+}
+QA_HD DD operator-(DD a) { return DD{-a.hi, -a.lo}; }
+QA_HD DD operator-(DD a, DD b) { return a + (-b); }
+QA_HD DD operator*(DD a, DD b) {
+    DD p = two_prod(a.hi, b.hi);
+    p.lo += a.hi * b.lo + a.lo * b.hi;
+    return quick_two_sum(p.hi, p.lo);
+}
+QA_HD DD operator*(DD a, double c) {
+    DD p = two_prod(a.hi, c);
+    p.lo += a.lo * c;
+    return quick_two_sum(p.hi, p.lo);
+}
+QA_HD DD operator/(DD a, DD b) {
+    double q1 = a.hi / b.hi;
+    DD r = a - b * q1;
+    double q2 = r.hi / b.hi;
+    r = r - b * q2;
+    double q3 = r.hi / b.hi;
+    DD q = quick_two_sum(q1, q2);
+    return q + dd(q3);
+}
+QA_HD DD& operator+=(DD& x, DD y) { x = x + y; return x; }
+QA_HD DD& operator*=(DD& x, DD y) { x = x * y; return x; }
+QA_HD DD fma_(DD a, DD b, DD c) { return a * b + c; }
+QA_HD double val(DD x) { return x.hi + x.lo; }
+QA_HD double mag(DD x) { return fabs(x.hi); }
+QA_HD DD sqrt_(DD a) {
+    double x = sqrt(a.hi);
+    DD r = a - two_prod(x, x);
+    return quick_two_sum(x, r.hi / (2.0 * x));
+}
+QA_HD double sqrt_(double a) { return sqrt(a); }
+QA_HD DD operator/(DD a, double b) { return a / dd(b); }
+
+template <class T> QA_HD T from_d(double x);
+// geometry storage type of an evaluation type, and the lift from storage
+template <class T> struct GeoOf { using type = double; };
+template <> struct GeoOf<DD> { using type = DD; };
+QA_HD double lift(double x, double*) { return x; }
+QA_HD EB lift(double x, EB*) { return EB{x, fabs(x)}; }
+QA_HD DD lift(DD x, DD*) { return x; }
+template <class T, class S> QA_HD T lift_to(S x) { return lift(x, (T*)nullptr); }
+template <> QA_HD double from_d<double>(double x) { return x; }
+template <> QA_HD EB from_d<EB>(double x) { return eb(x); }
+template <> QA_HD DD from_d<DD>(double x) { return dd(x); }

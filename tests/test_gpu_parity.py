@@ -1,0 +1,218 @@
+"""GPU parity: the HIP path against the oracle on the same seeded inputs.
+
+Bars: sectors and graph/forest lists bit-exact; z and log p to rounding;
+per-point f within 1e-10 of the oracle relative to the sum of the absolute
+forest-term values (the conditioning scale of the subtraction); integrals
+within the combined Monte Carlo sigma; the running error bound covers the
+FP64 - double-double difference."""
+import math
+
+import numpy as np
+import pytest
+
+import paper_1905_08007_amd as P
+from oracle import graphs as GR, integrand as IN, mc, pdf as PD
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+_CACHE = {}
+
+
+def setup(n, cls=None, first=None):
+    key = (n, cls, first)
+    if key not in _CACHE:
+        gs = P.enumerate_graphs(n, *(cls or (-1, -1, -1)))
+        if first:
+            gs = gs[:first]
+        s = P.build_forests(gs)
+        p = P.pdf_create(s)
+        img = P.upload(s, p)
+        og = [GR.enumerate_graphs(n)[i] for i in range(len(gs))] if cls is None else None
+        _CACHE[key] = (gs, s, p, img, og)
+    return _CACHE[key]
+
+
+def sync():
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_sample_pdf_matches_oracle(n):
+    gs, s, p, img, og = setup(n)
+    gi = len(gs) - 1
+    seed, tag, first, count = 17, 0, 1000, 200
+    z, lp, sec = P.sample_pdf(img, gi, seed, tag, first, count, want_sector=True)
+    sync()
+    z, lp, sec = z.cpu().numpy(), lp.cpu().numpy(), sec.cpu().numpy()
+    D = PD.deg_table(og[gi])
+    W = PD.w_table(D, 3 * n)
+    ref = PD.sample_stream(og[gi], D, W, seed, tag, gi, first, count)
+    for i, (zo, lo, order) in enumerate(ref):
+        assert list(sec[:, i]) == order
+        assert np.max(np.abs(z[:, i] - zo) / zo) < 1e-12
+        assert abs(lp[i] - lo) < 1e-11 * max(1.0, abs(lo))
+
+
+def _eval_cmp(n, gis, npts, seed):
+    gs, s, p, img, og = setup(n)
+    M = 3 * n
+    worst = 0.0
+    for gi in gis:
+        zs = np.concatenate([inputs.simplex_points(M, npts, seed + gi), inputs.boundary_points(M, npts // 2, seed + 100 + gi)])
+        zt = torch.from_numpy(np.ascontiguousarray(zs.T)).cuda()
+        f, _, _ = P.eval_integrand(img, gi, zt, P.QA_FP64)
+        sync()
+        f = f.cpu().numpy()
+        of = IN.Integrand(og[gi])
+        for i, zz in enumerate(zs):
+            v, terms = of(zz, True)
+            scale = sum(abs(t) for t in terms)
+            e = abs(f[i] - v) / scale
+            worst = max(worst, e)
+            assert e <= 1e-10, (gi, i, f[i], v, scale)
+    return worst
+
+
+def test_eval_matches_oracle_1loop():
+    _eval_cmp(1, [0], 130, 1)
+
+
+def test_eval_matches_oracle_2loop():
+    _eval_cmp(2, range(4), 70, 2)
+
+
+def test_eval_matches_oracle_3loop():
+    _eval_cmp(3, [0, 4, 8, 14, 19, 27], 24, 3)
+
+
+def test_eval_matches_oracle_4loop():
+    _eval_cmp(4, [0, 100, 268], 4, 4)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_bound_covers_double_double(n):
+    gs, s, p, img, og = setup(n)
+    M = 3 * n
+    for gi in range(min(len(gs), 6)):
+        zs = np.concatenate([inputs.simplex_points(M, 64, 50 + gi), inputs.boundary_points(M, 64, 60 + gi, lam=1e-9)])
+        zt = torch.from_numpy(np.ascontiguousarray(zs.T)).cuda()
+        f0, _, _ = P.eval_integrand(img, gi, zt, P.QA_FP64)
+        fb, eb, flag = P.eval_integrand(img, gi, zt, P.QA_FP64_BOUND)
+        fd, ed, _ = P.eval_integrand(img, gi, zt, P.QA_DD)
+        sync()
+        f0, fb, eb, flag = f0.cpu().numpy(), fb.cpu().numpy(), eb.cpu().numpy(), flag.cpu().numpy()
+        fd, ed = fd.cpu().numpy(), ed.cpu().numpy()
+        assert np.all(np.abs(fb - f0) <= 1e-13 * np.abs(f0) + eb)
+        assert np.all(np.abs(fb - fd) <= eb + ed)
+        assert np.array_equal(flag.astype(bool), ~(eb <= 1e-11 * np.abs(fb)))
+        assert np.all(ed <= 1e-20 * np.abs(fd) + eb * 1e-10)
+
+
+def test_accumulate_compensated():
+    rng = np.random.default_rng(3)
+    count = 100003
+    f = rng.standard_normal(count) * 1e3
+    lp = rng.standard_normal(count)
+    f[17] = np.nan
+    acc = P.new_acc(1)
+    P.accumulate(torch.from_numpy(f).cuda(), torch.from_numpy(lp).cuda(), acc)
+    sync()
+    a = P.read_acc(acc)[0]
+    w = f * np.exp(-lp)
+    good = np.isfinite(w)
+    assert int(a["n"]) == good.sum() and int(a["n_bad"]) == 1
+    s1 = math.fsum(w[good])
+    s2 = math.fsum(w[good] ** 2)
+    assert abs(a["s1_hi"] + a["s1_lo"] - s1) <= 1e-12 * abs(s1) + 1e-9
+    assert abs(a["s2_hi"] + a["s2_lo"] - s2) <= 1e-13 * s2
+
+
+def _plain_integral(n, per_graph, seed, chunk=1 << 20):
+    gs, s, p, img, og = setup(n)
+    acc = P.new_acc(len(gs))
+    for gi in range(len(gs)):
+        done = 0
+        while done < per_graph:
+            c = min(chunk, per_graph - done)
+            z, lp, _ = P.sample_pdf(img, gi, seed, 0, done, c)
+            f, _, _ = P.eval_integrand(img, gi, z, P.QA_FP64)
+            P.accumulate(f, lp, acc, gi)
+            done += c
+    sync()
+    a = P.read_acc(acc)
+    est = P.estimates(a, [g.mult for g in gs])
+    return a, est
+
+
+def test_one_loop_integral_is_half():
+    a, est = _plain_integral(1, 2_000_000, 1)
+    v, e = est[0]
+    assert abs(v - 0.5) < 4 * e, (v, e)
+    assert e < 0.003
+
+
+def test_two_loop_sum_matches_closed_form_and_oracle():
+    import json
+    import os
+    a, est = _plain_integral(2, 2_000_000, 2)
+    v = sum(x for x, _ in est)
+    e = math.sqrt(sum(x * x for _, x in est))
+    exact = -0.3441663874
+    assert abs(v - exact) < 4 * e, (v, e)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_2loop.json")))
+    for (x, ex), gg in zip(est, gold["graphs"]):
+        comb = math.sqrt(ex * ex + gg["sigma"] ** 2)
+        assert abs(x - gg["value"]) < 4.5 * comb, (x, gg["value"], comb)
+
+
+def test_batched_matches_plain():
+    gs, s, p, img, og = setup(2)
+    budgets = [100_003, 64, 70_001, 1]
+    acc = P.integrate(s, img, budgets, seed=5, tag=0, tile=512)
+    sync()
+    a = P.read_acc(acc)
+    accp = P.new_acc(len(gs))
+    for gi, b in enumerate(budgets):
+        z, lp, _ = P.sample_pdf(img, gi, 5, 0, 0, b)
+        f, _, _ = P.eval_integrand(img, gi, z, P.QA_FP64)
+        P.accumulate(f, lp, accp, gi)
+    sync()
+    ap = P.read_acc(accp)
+    for x, y, b in zip(a, ap, budgets):
+        assert int(x["n"]) + int(x["n_bad"]) == b
+        assert int(x["n"]) == int(y["n"])
+        s1x, s1y = x["s1_hi"] + x["s1_lo"], y["s1_hi"] + y["s1_lo"]
+        s2x, s2y = x["s2_hi"] + x["s2_lo"], y["s2_hi"] + y["s2_lo"]
+        assert abs(s1x - s1y) <= 1e-9 * math.sqrt(s2y * max(1, int(y["n"]))) + 1e-300
+        assert abs(s2x - s2y) <= 1e-9 * s2y + 1e-300
+    # deterministic: a second run is bit-identical
+    acc2 = P.integrate(s, img, budgets, seed=5, tag=0, tile=512)
+    sync()
+    assert P.read_acc(acc2).tobytes() == a.tobytes()
+
+
+def test_variance_grad_matches_oracle():
+    gs, s, p, img, og = setup(2)
+    gi, seed, tag, count = 1, 4, 1, 512
+    m2, g = P.variance_and_grad(s, p, img, gi, seed, tag, 0, count)
+    smp = mc.graph_samples(og[gi], gi, seed, 0, count, tag=tag)
+    D, _ = p.tables(gi)
+    go = mc.variance_grad(smp, D, 6)
+    m2o = sum(w * w for *_, w, _o in [(a, b, c, d, e) for a, b, c, d, e in smp]) / count
+    assert abs(m2 - m2o) < 1e-9 * m2o
+    assert np.allclose(g, go, rtol=1e-8, atol=1e-10 * np.max(np.abs(go)))
+
+
+def test_edge_cases():
+    gs, s, p, img, og = setup(2)
+    z = torch.empty((6, 0), dtype=torch.float64, device="cuda")
+    f, _, _ = P.eval_integrand(img, 0, z)
+    assert f.numel() == 0
+    with pytest.raises(RuntimeError):
+        P.sample_pdf(img, 99, 1, 0, 0, 10)
+    z1, lp1, _ = P.sample_pdf(img, 3, 8, 0, 12345, 1)
+    f1, _, _ = P.eval_integrand(img, 3, z1)
+    sync()
+    assert np.isfinite(f1.cpu().numpy()).all()
