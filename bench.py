@@ -1,0 +1,184 @@
+"""Throughput of the 5-loop subtracted-integrand Monte Carlo hot path on one GPU.
+
+Workload: the 73 representatives of the gauge-invariant class (5,0,0) of
+5-loop vertex graphs without lepton loops (Table 1), batched form: one
+persistent fused launch per round (Philox -> sector PDF -> graph polynomials
+-> forest-formula integrand in FP64 with a running error bound -> f/p ->
+compensated per-tile sums), flagged points recomputed in double-double,
+deterministic reduction, all rounds of a step replayed from one hipGraph.
+A step is one pass over a batch of `--samples` points split evenly over the
+73 graphs (each step uses fresh sample indices of the same Philox stream).
+
+Prints one JSON line (see README of the build for the field meanings).
+"""
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+METRIC = "5-loop subtracted integrand evals/s on 1 GPU; MC σ reached per GPU-hour"
+SEED = 5
+
+
+def oracle_baseline(q, seconds):
+    """CPU baseline: the oracle (test infrastructure) on one host core, for one
+    graph of class (5,0,0): sector sampling + subtracted integrand + f/p, after
+    its one-time table setup (reported separately)."""
+    try:
+        from oracle import graphs as GR, mc
+        g = GR.enumerate_graphs(5, (5, 0, 0))[1]
+        t0 = time.time()
+        mc.graph_samples(g, 1, SEED, 0, 1, tag=2)        # builds the oracle's monomial tables
+        setup = time.time() - t0
+        n = 0
+        t0 = time.time()
+        while time.time() - t0 < seconds:
+            mc.graph_samples(g, 1, SEED, 1 + n, 4, tag=2)
+            n += 4
+        dt = time.time() - t0
+        q.put({"value": n / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n} points of graph 1 of class (5,0,0) (x={g['x']}), sampling + f + f/p, "
+                         f"{dt:.1f} s on one core after {setup:.1f} s one-time setup"})
+    except Exception as e:  # noqa: BLE001
+        q.put({"error": repr(e)})
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--samples", type=int, default=1 << 23, help="samples per step over the 73 graphs")
+    ap.add_argument("--tile", type=int, default=1024)
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+              "the hot path shards by graph / sample range without communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1905_08007_amd as P
+
+    t0 = time.time()
+    graphs = P.enumerate_graphs(5, 5, 0, 0)
+    gset = P.build_forests(graphs, args.threads)
+    pdf = P.pdf_create(gset)
+    img = P.upload(gset, pdf, device="cuda:0")
+    setup_s = time.time() - t0
+    ng = len(graphs)
+    per = args.samples // ng
+    budgets = np.full(ng, per, dtype=np.uint64)
+    flops = [gset.flops(i) for i in range(ng)]
+    eval_flops_step = float(sum(per * a for a, _ in flops))
+    all_flops_step = float(sum(per * (a + b) for a, b in flops))
+
+    q = None
+    proc = None
+    if not args.no_cpu_baseline:
+        ctx = mp.get_context("spawn")
+        q = ctx.Queue()
+        proc = ctx.Process(target=oracle_baseline, args=(q, args.cpu_seconds))
+        proc.start()
+
+    work = torch.empty(P.work_bytes(gset, budgets, args.tile), dtype=torch.uint8, device="cuda:0")
+    accs = []
+    step = 0
+    for _ in range(args.warmup):
+        P.integrate(gset, img, budgets, SEED, 0, args.tile, args.grid, work=work, first=step * per)
+        step += 1
+    torch.cuda.synchronize()
+    fused_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        acc, ms = P.integrate(gset, img, budgets, SEED, 0, args.tile, args.grid, work=work, first=step * per,
+                              timing=True)
+        accs.append(acc)
+        fused_ms += ms
+        step += 1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    # per-graph sums over the timed steps
+    tot = np.zeros(ng, dtype=[("n", "f8"), ("s1", "f8"), ("s2", "f8"), ("flag", "f8"), ("bad", "f8")])
+    for acc in accs:
+        a = P.read_acc(acc)
+        tot["n"] += a["n"]
+        tot["s1"] += a["s1_hi"] + a["s1_lo"]
+        tot["s2"] += a["s2_hi"] + a["s2_lo"]
+        tot["flag"] += a["n_flagged"]
+        tot["bad"] += a["n_bad"]
+    val, var = 0.0, 0.0
+    for i, g in enumerate(graphs):
+        n = tot["n"][i]
+        m = tot["s1"][i] / n
+        v = (tot["s2"][i] / n - m * m) / (n - 1)
+        val += g.mult * m
+        var += g.mult ** 2 * v
+    sigma = math.sqrt(var)
+    samples = float(per * ng * args.steps)
+    evals_s = samples / dt
+    sigma_gpu_hour = sigma * math.sqrt(dt / 3600.0)
+    achieved = eval_flops_step * args.steps / (fused_ms * 1e-3) / 1e12
+
+    cpu = None
+    if proc is not None:
+        proc.join(timeout=600)
+        cpu = q.get() if not q.empty() else {"error": "oracle baseline did not report"}
+
+    out = {
+        "metric": METRIC,
+        "value": evals_s,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "5-loop QED vertex graphs without lepton loops, class (5,0,0), 73 graphs; batched "
+                        "persistent hipGraph launch, FP64 with running error bound and double-double recompute",
+            "samples_per_step": int(per * ng),
+            "tile": args.tile,
+            "grid": args.grid,
+            "seed": SEED,
+            "sigma_per_gpu_hour": sigma_gpu_hour,
+            "class_value": val,
+            "class_sigma": sigma,
+            "flagged_fraction": float(tot["flag"].sum() / max(1.0, tot["n"].sum())),
+            "bad_points": int(tot["bad"].sum()),
+            "host_setup_s": setup_s,
+            "fused_kernel_ms_per_step": fused_ms / args.steps,
+            "eval_flops_per_sample": eval_flops_step / (per * ng),
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": None,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

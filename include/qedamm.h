@@ -52,7 +52,13 @@ typedef struct qa_acc {
 } qa_acc;
 
 typedef struct qa_set qa_set;   /* graphs + forests + integrand tables (host) */
-typedef struct qa_pdf qa_pdf;   /* Deg and W tables of eq. (1) (host) */
+typedef struct qa_pdf qa_pdf;   /* Algorithmic FP64 operation count of one plain evaluation of graph i's
+ * integrand (graph polynomials of every piece, every coefficient-table block
+ * with its multilinear fold, forest-term combination) plus the sector
+ * sampler; an FMA counts 2.  Used for the roofline of the integrand kernel. */
+int qa_graph_flops(const qa_set* s, uint32_t graph, double* eval_flops, double* sample_flops);
+
+/* Deg and W tables of eq. (1) (host) */
 
 const char* qa_last_error(void);
 
@@ -81,6 +87,12 @@ int qa_forests_serialize(const qa_set* s, void* buf, size_t cap, size_t* len);
 
 /* Statistics of the coefficient tables: monomial blocks, coefficients, terms. */
 int qa_set_stats(const qa_set* s, uint64_t* nterms, uint64_t* nblocks, uint64_t* ncoef);
+
+/* Algorithmic FP64 operation count of one plain evaluation of graph i's
+ * integrand (graph polynomials of every piece, every coefficient-table block
+ * with its multilinear fold, forest-term combination) plus the sector
+ * sampler; an FMA counts 2.  Used for the roofline of the integrand kernel. */
+int qa_graph_flops(const qa_set* s, uint32_t graph, double* eval_flops, double* sample_flops);
 
 /* Deg and W tables of eq. (1) for every graph of the set.  deg == NULL: the
  * default Deg rule (parametric UV degree of the I-closure, minimised over the
@@ -122,14 +134,20 @@ int qa_eval_integrand(const void* dev, uint32_t graph, const double* z, uint64_t
 int qa_accumulate(const double* f, const double* logp, uint64_t count, qa_acc* acc, void* stream);
 
 /* Batched form: all graphs of the set with per-graph budgets (host array,
- * samples per graph, first sample index 0), fused sample + evaluate (FP64
- * with error bound) + accumulate in one persistent launch, flagged points
- * recomputed in double-double, deterministic per-tile partials reduced into
- * acc (device, ng records, overwritten).  work (device) >= qa_work_bytes.
- * tile = samples per tile (multiple of 64, 0 = default). */
+ * samples per graph; graph g uses samples first .. first+budgets[g]-1 of its
+ * stream), fused sample + evaluate (FP64 with the running error bound) +
+ * accumulate in a persistent launch (waves pull tiles of `tile` samples from
+ * a queue), flagged points recomputed in double-double, deterministic
+ * per-tile partials reduced into acc (device, ng records, overwritten).  The
+ * work is split into rounds of 2048 tiles; one round is captured as a
+ * hipGraph and replayed.  work (device) >= qa_work_bytes.  tile = multiple of
+ * 64 (0 = 1024); grid = persistent waves (0 = 4 per CU, max 2048).
+ * fused_ms (host, nullable): receives the summed duration of the fused
+ * kernel over all rounds, from HIP events on `stream`. */
 int qa_work_bytes(const qa_set* s, const uint64_t* budgets, uint32_t tile, size_t* bytes);
-int qa_integrate(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t seed, uint32_t tag,
-                 uint32_t tile, uint32_t grid, void* work, size_t work_bytes, qa_acc* acc, void* stream);
+int qa_integrate(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t first, uint64_t seed,
+                 uint32_t tag, uint32_t tile, uint32_t grid, void* work, size_t work_bytes, qa_acc* acc,
+                 double* fused_ms, void* stream);
 
 /* Variance gradient (pilot runs): for graph `graph`, samples first..first+
  * count-1 of stream (seed, tag): grad (device, 2^M doubles, accumulated +=)

@@ -15,7 +15,35 @@ Method: textbook 4-dimensional contraction identities (Chisholm):
 applied to an innermost-first choice of contracted pair, and p-slash p-slash = 1.
 When no contracted pair is left the string is a power of p-slash.
 """
+import ctypes
+import os
 from functools import lru_cache
+
+_C = None
+
+
+def _ctrace():
+    """The plain-C port of the same recursion (oracle/_ctrace.so), if built."""
+    global _C
+    if _C is None:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_ctrace.so")
+        if os.path.exists(path):
+            lib = ctypes.CDLL(path)
+            lib.oracle_trace.restype = ctypes.c_longlong
+            lib.oracle_trace.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+            _C = lib
+        else:
+            _C = False
+    return _C or None
+
+
+def trace_fast(s):
+    """Same value as trace(s); uses the C port when it is built."""
+    lib = _ctrace()
+    if lib is None or len(s) > 60:
+        return trace(s)
+    arr = (ctypes.c_int * len(s))(*s)
+    return int(lib.oracle_trace(arr, len(s)))
 
 
 def _canon(s):

@@ -19,6 +19,11 @@ definitions are not printed in the paper; the readings used here are:
         A on gamma; L on the elements of F strictly between gamma and G;
         (L - U) on G when gamma != G; U on every other element of F.
 
+Arithmetic: long double (x87, unit round-off 2^-64) for the graph
+polynomials, the monomial sums and the term combination, or mpmath at 60
+significant digits (set_precision("mp")) for ill-conditioned points; Dirac
+traces and table coefficients are exact rationals until converted.
+
 A forest term is the product of the operator outputs of its pieces (each
 element of F with its maximal sub-elements contracted), written as one
 parametric integral over all lines of G (Schwinger form, common scale):
@@ -36,7 +41,7 @@ from math import gamma as Gamma
 import numpy as np
 
 from . import graphs as GR
-from .dirac import trace
+from .dirac import trace_fast as trace
 
 # ----------------------------------------------------------------------------
 # structure: terms and pieces
@@ -298,7 +303,7 @@ def _piece_monomials(sig):
                     ps = tuple(sorted(s for s, c in ch.items() if c == "p"))
                     key = (k, tuple(pairs), ps, qs)
                     acc[key] = acc.get(key, 0) + total
-    return tuple((k, float(c), pr, ps, qs) for (k, pr, ps, qs), c in sorted(acc.items(), key=lambda t: str(t[0])) if c)
+    return tuple((k, c, pr, ps, qs) for (k, pr, ps, qs), c in sorted(acc.items(), key=lambda t: str(t[0])) if c)
 
 
 def _piece_signature(piece, variant):
@@ -332,39 +337,94 @@ def _piece_signature(piece, variant):
 # geometry at a point
 
 
+LD = np.longdouble
+
+# numeric context: dtype of arrays and the conversion of floats / rationals
+_NUM = {"mode": "ld", "dtype": LD, "conv": LD}
+
+
+def set_precision(mode="ld", dps=60):
+    """'ld' (long double, vectorised) or 'mp' (mpmath, dps digits)."""
+    if mode == "ld":
+        _NUM.update(mode="ld", dtype=LD, conv=LD)
+    else:
+        import mpmath
+        mpmath.mp.dps = dps
+        _NUM.update(mode="mp", dtype=object, conv=mpmath.mpf)
+
+
+def _c(x):
+    """Convert a float or Fraction into the working precision."""
+    conv = _NUM["conv"]
+    if isinstance(x, Fraction):
+        return conv(x.numerator) / conv(x.denominator)
+    return conv(x)
+
+
+def _spd_inverse_det(M):
+    """Determinant and inverse of a small symmetric positive definite matrix
+    by Gauss-Jordan elimination in long double."""
+    L = M.shape[0]
+    A = M.copy()
+    inv = np.zeros((L, L), dtype=_NUM["dtype"])
+    for i in range(L):
+        inv[i, i] = _c(1)
+    det = _c(1)
+    for c in range(L):
+        piv = A[c, c]
+        det *= piv
+        A[c] /= piv
+        inv[c] /= piv
+        for r in range(L):
+            if r != c:
+                fac = A[r, c]
+                A[r] -= fac * A[c]
+                inv[r] -= fac * inv[c]
+    return det, inv
+
+
 def piece_geometry(piece, z, g):
     """Loop matrix, U, flows A (momentum p) and C (momentum q), V, and the
-    Wick contraction matrix Bbar of the piece's electron lines at z."""
+    Wick contraction matrix Bbar of the piece's electron lines at z
+    (long double)."""
     n = g["n"]
     lines = piece["lines"]
     spans = piece["spans"]
-    ze = np.array([z[l] for l in lines])
+    dt = _NUM["dtype"]
+    ze = np.array([_c(float(z[l])) for l in lines], dtype=dt)
     L = len(spans)
     nl = len(lines)
-    eta = np.zeros((nl, L))
-    M = np.zeros((L, L))
+    eta = np.zeros((nl, L), dtype=dt)
+    eta[:] = _c(0)
+    M = np.zeros((L, L), dtype=dt)
+    M[:] = _c(0)
     for c, (a, sp) in enumerate(spans):
-        eta[sp, c] = 1.0
-        M[c, c] += z[2 * n + a]
+        eta[sp, c] = _c(1)
+        M[c, c] += _c(float(z[2 * n + a]))
     M += (eta * ze[:, None]).T @ eta
-    U = np.linalg.det(M)
-    Minv = np.linalg.inv(M)
+    U, Minv = _spd_inverse_det(M)
     j = eta.T @ ze
-    A = 1.0 - eta @ (Minv @ j)
+    A = _c(1) - eta @ (Minv @ j)
     ext = piece["ext"]
     if ext is not None:
-        Pq = np.array([-0.5 if ln < ext else 0.5 for ln in range(nl)])
+        Pq = np.array([_c(-0.5) if ln < ext else _c(0.5) for ln in range(nl)], dtype=dt)
         jq = eta.T @ (ze * Pq)
         C = Pq - eta @ (Minv @ jq)
     else:
-        C = np.zeros(nl)
-    V = float(np.sum(ze * (1.0 - A)))
+        C = np.array([_c(0)] * nl, dtype=dt)
+    V = np.sum(ze * (_c(1) - A))
     B = eta @ Minv @ eta.T
     return {"U": U, "A": A, "C": C, "V": V, "B": B}
 
 
+def _zeros(n):
+    out = np.zeros(n, dtype=_NUM["dtype"])
+    out[:] = _c(0)
+    return out
+
+
 def _poly_mul(a, b, n):
-    out = np.zeros(n)
+    out = _zeros(n)
     for i in range(n):
         if a[i] == 0:
             continue
@@ -373,21 +433,50 @@ def _poly_mul(a, b, n):
     return out
 
 
-def _eval_monomials(mons, slot_line, geo, n):
-    P = np.zeros(n)
-    A, C, B = geo["A"], geo["C"], geo["B"]
-    for k, coef, pairs, ps, qs in mons:
-        if k >= n:
-            continue
-        w = coef
-        for a, b in pairs:
-            w *= B[slot_line[a], slot_line[b]]
-        for s in ps:
-            w *= A[slot_line[s]]
+_PACKED = {}
+
+
+def _pack(mons, slot_line):
+    """Monomials as arrays: k, coef, pair line indices, p-slot lines, q line."""
+    key = (id(mons), tuple(sorted(slot_line.items())), _NUM["mode"])
+    if key in _PACKED:
+        return _PACKED[key]
+    m = len(mons)
+    K = np.zeros(m, dtype=np.int64)
+    coef = np.zeros(m, dtype=_NUM["dtype"])
+    P1 = np.full((m, 6), -1, dtype=np.int64)
+    P2 = np.full((m, 6), -1, dtype=np.int64)
+    AS = np.full((m, 14), -1, dtype=np.int64)
+    Q = np.full(m, -1, dtype=np.int64)
+    for i, (k, c, pairs, ps, qs) in enumerate(mons):
+        K[i] = k
+        coef[i] = _c(c)
+        for j, (a, b) in enumerate(pairs):
+            P1[i, j] = slot_line[a]
+            P2[i, j] = slot_line[b]
+        for j, sl in enumerate(ps):
+            AS[i, j] = slot_line[sl]
         if qs is not None:
-            w *= C[slot_line[qs]]
-        P[k] += w
-    return P
+            Q[i] = slot_line[qs]
+    _PACKED[key] = (mons, K, coef, P1, P2, AS, Q)
+    return _PACKED[key]
+
+
+def _eval_monomials(mons, slot_line, geo, n):
+    _, K, coef, P1, P2, AS, Q = _pack(mons, slot_line)
+    A, C, B = geo["A"], geo["C"], geo["B"]
+    nl = len(A)
+    dt = _NUM["dtype"]
+    Bp = np.zeros((nl + 1, nl + 1), dtype=dt)
+    Bp[:] = _c(1)
+    Bp[:nl, :nl] = B
+    Ap = np.append(A, _c(1)).astype(dt)
+    Cp = np.append(C, _c(1)).astype(dt)
+    w = coef * np.prod(Bp[P1, P2], axis=1) * np.prod(Ap[AS], axis=1) * Cp[Q]
+    keep = K < n
+    out = _zeros(n)
+    np.add.at(out, K[keep], w[keep])
+    return out
 
 
 def term_value(g, mask, apos, z, pieces=None):
@@ -401,14 +490,14 @@ def term_value(g, mask, apos, z, pieces=None):
     for i, p in enumerate(pieces):           # children first
         ins = [j for j, v in enumerate(p["vtype"]) if v[0] == "ins"]
         vkids = [k for k in p["kids"] if k["kind"] == "V"]
-        base = np.zeros(n)
-        base[0] = 1.0
+        base = _zeros(n)
+        base[0] = _c(1)
         for k in vkids:
             base = _poly_mul(base, out[key(k)], n)
         ops = ["Sa", "Sb"] if p["op"] == "US" else [p["op"]]
         res = []
         for op in ops:
-            tot = np.zeros(n)
+            tot = _zeros(n)
             for bits in range(1 << len(ins)):
                 variant = {j: ("b" if bits >> t & 1 else "a") for t, j in enumerate(ins)}
                 seq, slot_line = _piece_signature(p, variant)
@@ -422,14 +511,14 @@ def term_value(g, mask, apos, z, pieces=None):
         out[key(p["elem"])] = res if p["op"] == "US" else res[0]
     top = out[(0, 2 * n)]
     Vt = sum(gg["V"] for gg in geos)
-    pref = 1.0
+    pref = _c(1)
     for gg in geos:
         pref /= gg["U"] ** 2
-    s = 0.0
+    s = _c(0)
     for K in range(n):
-        s += top[K] * (-0.5) ** K * Gamma(n - K) * Vt ** (K - n)
-    sign = -1.0 if (bin(mask).count("1") + n) % 2 else 1.0
-    return sign * pref * s / 4.0 ** n
+        s += top[K] * _c((-0.5) ** K * Gamma(n - K)) * Vt ** (K - n)
+    sign = -1 if (bin(mask).count("1") + n) % 2 else 1
+    return sign * pref * s / _c(4) ** n
 
 
 class Integrand:
@@ -440,7 +529,10 @@ class Integrand:
         self.terms = [(m, a, term_pieces(g, m, a)) for m, a in graph_terms(g)]
 
     def __call__(self, z, return_terms=False):
+        """f_G(z) in long double, returned as a Python float (and the forest
+        terms as floats)."""
         vals = [term_value(self.g, m, a, z, pcs) for m, a, pcs in self.terms]
+        tot = sum(vals, _c(0))
         if return_terms:
-            return float(sum(vals)), vals
-        return float(sum(vals))
+            return float(tot), [float(v) for v in vals]
+        return float(tot)

@@ -58,8 +58,9 @@ def lib():
         L.qa_eval_integrand.argtypes = [vp, u32, vp, u64, i32, vp, vp, vp, vp]
         L.qa_accumulate.argtypes = [vp, vp, u64, vp, vp]
         L.qa_work_bytes.argtypes = [vp, vp, u32, C.POINTER(sz)]
-        L.qa_integrate.argtypes = [vp, vp, vp, u64, u32, u32, u32, vp, sz, vp, vp]
+        L.qa_integrate.argtypes = [vp, vp, vp, u64, u64, u32, u32, u32, vp, sz, vp, vp, vp]
         L.qa_variance_grad.argtypes = [vp, u32, u64, u32, u64, u64, vp, vp, vp]
+        L.qa_graph_flops.argtypes = [vp, u32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.qa_dirac_trace.argtypes = [vp, i32, C.POINTER(C.c_double)]
         _lib = L
     return _lib
@@ -123,6 +124,12 @@ class GraphSet:
         a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
         _check(lib().qa_set_stats(self.h, C.byref(a), C.byref(b), C.byref(c)), "qa_set_stats")
         return {"terms": a.value, "blocks": b.value, "coefficients": c.value}
+
+    def flops(self, g):
+        """(evaluation, sampling) algorithmic FP64 flops per sample of graph g."""
+        a, b = C.c_double(), C.c_double()
+        _check(lib().qa_graph_flops(self.h, g, C.byref(a), C.byref(b)), "qa_graph_flops")
+        return a.value, b.value
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -193,9 +200,15 @@ def upload(gset, pdf, device="cuda", stream=None):
 
 # --------------------------------------------------------------------------- hot path
 
+def _lines(img, graph):
+    if not 0 <= graph < len(img.gset.graphs):
+        raise RuntimeError(f"graph index {graph} out of range (set has {len(img.gset.graphs)} graphs)")
+    return 3 * img.gset.graphs[graph].loops
+
+
 def sample_pdf(img, graph, seed, tag, first, count, want_sector=False, stream=None):
     import torch
-    M = 3 * img.gset.graphs[graph].loops
+    M = _lines(img, graph)
     dev = img.buf.device
     z = torch.empty((M, count), dtype=torch.float64, device=dev)
     logp = torch.empty(count, dtype=torch.float64, device=dev)
@@ -208,7 +221,8 @@ def sample_pdf(img, graph, seed, tag, first, count, want_sector=False, stream=No
 def eval_integrand(img, graph, z, mode=QA_FP64, stream=None):
     import torch
     M, count = z.shape
-    assert M == 3 * img.gset.graphs[graph].loops and z.dtype == torch.float64 and z.is_contiguous()
+    if M != _lines(img, graph) or z.dtype != torch.float64 or not z.is_contiguous():
+        raise RuntimeError("z must be a contiguous float64 tensor of shape (3n, count)")
     f = torch.empty(count, dtype=torch.float64, device=z.device)
     err = torch.empty(count, dtype=torch.float64, device=z.device) if mode != QA_FP64 else None
     flag = torch.empty(count, dtype=torch.uint8, device=z.device) if mode == QA_FP64_BOUND else None
@@ -251,8 +265,10 @@ def work_bytes(gset, budgets, tile=0):
     return n.value
 
 
-def integrate(gset, img, budgets, seed, tag=0, tile=0, grid=0, work=None, acc=None, stream=None):
-    """Batched form: one persistent launch per round under a hipGraph."""
+def integrate(gset, img, budgets, seed, tag=0, tile=0, grid=0, work=None, acc=None, first=0, timing=False,
+              stream=None):
+    """Batched form: persistent fused launches under a hipGraph.  Returns acc,
+    or (acc, fused-kernel milliseconds) with timing=True."""
     import torch
     b = np.ascontiguousarray(budgets, dtype=np.uint64)
     dev = img.buf.device
@@ -260,14 +276,16 @@ def integrate(gset, img, budgets, seed, tag=0, tile=0, grid=0, work=None, acc=No
         work = torch.empty(work_bytes(gset, b, tile), dtype=torch.uint8, device=dev)
     if acc is None:
         acc = new_acc(len(gset), dev)
-    _check(lib().qa_integrate(gset.h, img.ptr, b.ctypes.data_as(C.c_void_p), seed, tag, tile, grid, _ptr(work),
-                              work.numel(), _ptr(acc), _stream(stream)), "qa_integrate")
-    return acc
+    ms = C.c_double(0.0)
+    _check(lib().qa_integrate(gset.h, img.ptr, b.ctypes.data_as(C.c_void_p), first, seed, tag, tile, grid,
+                              _ptr(work), work.numel(), _ptr(acc), C.byref(ms) if timing else None,
+                              _stream(stream)), "qa_integrate")
+    return (acc, ms.value) if timing else acc
 
 
 def variance_grad(img, graph, seed, tag, first, count, grad=None, w2sum=None, stream=None):
     import torch
-    M = 3 * img.gset.graphs[graph].loops
+    M = _lines(img, graph)
     dev = img.buf.device
     if grad is None:
         grad = torch.zeros(1 << M, dtype=torch.float64, device=dev)

@@ -23,7 +23,7 @@ def build(verbose=False, jobs=8):
         os.makedirs(os.path.dirname(obj), exist_ok=True)
         path = os.path.join(CSRC, src)
         if src.endswith(".hip"):
-            cmd = [hipcc, "-x", "hip", f"--offload-arch={ARCH}", "-ffp-contract=fast",
+            cmd = [hipcc, "-x", "hip", f"--offload-arch={ARCH}", "-ffp-contract=fast-honor-pragmas",
                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                    "-munsafe-fp-atomics"] + common + ["-c", path, "-o", obj]
         else:

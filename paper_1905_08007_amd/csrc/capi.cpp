@@ -192,6 +192,63 @@ extern "C" int qa_set_stats(const qa_set* s, uint64_t* nterms, uint64_t* nblocks
     return QA_OK;
 }
 
+// FP64 operations of geometry_L for a piece (mirrors its loops)
+static double geometry_flops(const Piece& p) {
+    const int L = (int)p.chords.size(), nl = (int)p.lines.size();
+    auto span = [&](int c, int i) { return i >= p.chords[c][1] && i < p.chords[c][2]; };
+    double f = 0;
+    for (int c = 0; c < L; ++c)
+        for (int d = c; d < L; ++d) {
+            for (int i = 0; i < nl; ++i) f += span(c, i) && span(d, i);
+            f += (c == d);
+        }
+    for (int c = 0; c < L; ++c) { for (int d = 0; d <= c; ++d) f += 2 * d + 1; }   // Cholesky (sqrt / div as 1)
+    f += 2 * L;                                                                      // U
+    for (int c = 0; c < L; ++c) { f += 1; for (int d = 0; d < c; ++d) f += 2 * (c - d) + 1; }
+    for (int c = 0; c < L; ++c) for (int d = c; d < L; ++d) f += 2 * (L - d);         // M^-1
+    for (int c = 0; c < L; ++c) for (int i = 0; i < nl; ++i) f += 2 * span(c, i);     // jq
+    f += 4.0 * L * L;                                                                 // y, yq
+    for (int i = 0; i < nl; ++i) {
+        int ns = 0;
+        for (int c = 0; c < L; ++c) ns += span(c, i);
+        f += 2 * ns + 3 + (double)L * ns;                                              // A, C, V, Y
+        for (int j = i; j < nl; ++j) { for (int d = 0; d < L; ++d) f += span(d, j); }
+    }
+    return f;
+}
+
+static double table_flops(const Table& t, int n) {
+    double f = n;  // scale
+    for (auto& b : t.blocks) {
+        f += b.k > 1 ? b.k - 1 : 0;
+        f += 2.0 * ((1 << b.r) - 1);
+        if (t.has_q) f += b.r * (2.0 * ((1 << (b.r > 0 ? b.r - 1 : 0)) - 1) + 2);
+        f += 2;
+    }
+    return f;
+}
+
+extern "C" int qa_graph_flops(const qa_set* s, uint32_t graph, double* eval_flops, double* sample_flops) {
+    if (!s || graph >= s->graphs.size()) return fail(QA_EINVAL, "bad graph index");
+    const auto& T = s->graphs[graph];
+    const int n = T.g.n, M = 3 * n;
+    double f = 0;
+    for (size_t ti = 0; ti < T.terms.size(); ++ti) {
+        for (size_t pi = 0; pi < T.pieces[ti].size(); ++pi) {
+            const Piece& p = T.pieces[ti][pi];
+            f += geometry_flops(p) + 4;  // + U^-2, V sum
+            int nins = 0, nv = 0;
+            for (auto& nd : p.nodes) { nins += nd.vtype == 2; nv += nd.kid >= 0 && nd.vtype != 2; }
+            for (auto& tb : T.tabs[ti][pi]) f += table_flops(tb, n) + nins * n * (n + 1.0) + n;
+            f += nv * n * (n + 1.0);
+        }
+        f += 6.0 * n + 4;  // K sum, prefactors
+    }
+    if (eval_flops) *eval_flops = f;
+    if (sample_flops) *sample_flops = 1.5 * M * M + 50.0 * M;  // sector tree adds, log/exp as ~20 each
+    return QA_OK;
+}
+
 extern "C" int qa_pdf_create(const qa_set* s, const double* deg, qa_pdf** out) {
     try {
         if (!s || !out) return fail(QA_EINVAL, "NULL argument");
@@ -336,7 +393,7 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
                     DevTable dtb{};
                     dtb.nblocks = (int)tb.blocks.size();
                     dtb.has_q = tb.has_q;
-                    dtb.scale = tb.scale;
+                    dtb.denom = 1.0 / tb.scale;
                     dtb.hdr_off = hoff;
                     dtb.coef_off = coff;
                     std::memcpy(P.buf.data() + taboff + k * sizeof(DevTable), &dtb, sizeof dtb);

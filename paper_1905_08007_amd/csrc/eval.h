@@ -23,8 +23,10 @@ QA_HD int tri_idx(int a, int b) { return a <= b ? b * (b + 1) / 2 + a : a * (a +
 // Wick contraction matrix Bbar_ij = eta_i^T M^-1 eta_j, flows A (external p
 // from the first to the last node) and C (q entering at the external node,
 // -1/2 leaving at each end), V = sum_i z_i (1 - A_i).
-template <class T, int L>
-QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<T> vars, T& U, T& V, double& cond) {
+// computed in double-double (T = DD); results stored as S (double or DD)
+template <class S, int L>
+QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V, double& cond) {
+    using T = DD;
     const int nl = pc.nlines;
     T zl[QA_MAXL];
 #pragma unroll
@@ -119,14 +121,14 @@ QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<T> vars, T& U, T& V,
     T Y[QA_MAXL][L];
 #pragma unroll
     for (int i = 0; i < QA_MAXL; ++i) {
-        if (i >= nl) break;
+        if (i < nl) {
         T a = from_d<T>(1.0), cq = from_d<T>(hq ? (i < pc.ext ? -0.5 : 0.5) : 0.0);
 #pragma unroll
         for (int c = 0; c < L; ++c)
             if (in[i][c]) { a = a - y[c]; cq = cq - yq[c]; }
         if (!hq) cq = from_d<T>(0.0);
-        vars[QA_VAR_A + i] = a;
-        vars[QA_VAR_C + i] = cq;
+        store_geo(vars[QA_VAR_A + i], a);
+        store_geo(vars[QA_VAR_C + i], cq);
         V = V + zl[i] * (from_d<T>(1.0) - a);
 #pragma unroll
         for (int d = 0; d < L; ++d) {
@@ -136,30 +138,31 @@ QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<T> vars, T& U, T& V,
                 if (in[i][c]) s = s + Mi[c][d];
             Y[i][d] = s;
         }
+        }
     }
 #pragma unroll
     for (int i = 0; i < QA_MAXL; ++i) {
-        if (i >= nl) break;
 #pragma unroll
         for (int j = i; j < QA_MAXL; ++j) {
-            if (j >= nl) break;
-            T s = from_d<T>(0.0);
+            if (j < nl) {
+                T s = from_d<T>(0.0);
 #pragma unroll
-            for (int d = 0; d < L; ++d)
-                if (in[j][d]) s = s + Y[i][d];
-            vars[tri_idx(i, j)] = s;
+                for (int d = 0; d < L; ++d)
+                    if (in[j][d]) s = s + Y[i][d];
+                store_geo(vars[tri_idx(i, j)], s);
+            }
         }
     }
 }
 
-template <class T>
-QA_HD void geometry(const DevPiece& pc, CLV<double> z, LV<T> vars, T& U, T& V, double& cond) {
+template <class S>
+QA_HD void geometry(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V, double& cond) {
     switch (pc.nchords) {
-        case 1: geometry_L<T, 1>(pc, z, vars, U, V, cond); break;
-        case 2: geometry_L<T, 2>(pc, z, vars, U, V, cond); break;
-        case 3: geometry_L<T, 3>(pc, z, vars, U, V, cond); break;
-        case 4: geometry_L<T, 4>(pc, z, vars, U, V, cond); break;
-        default: geometry_L<T, 5>(pc, z, vars, U, V, cond); break;
+        case 1: geometry_L<S, 1>(pc, z, vars, U, V, cond); break;
+        case 2: geometry_L<S, 2>(pc, z, vars, U, V, cond); break;
+        case 3: geometry_L<S, 3>(pc, z, vars, U, V, cond); break;
+        case 4: geometry_L<S, 4>(pc, z, vars, U, V, cond); break;
+        default: geometry_L<S, 5>(pc, z, vars, U, V, cond); break;
     }
 }
 
@@ -204,8 +207,10 @@ template <class T> QA_HD T fold(const double* c, const T* A, int r) {
 // Evaluate one coefficient table: poly[k] = scale * sum over blocks with k pairs
 template <class T, class S>
 QA_HD void eval_table(const uint8_t* __restrict__ img, const DevTable& tb, LV<S> vars, int n, T* poly) {
+    using AT = typename Acc<T>::type;
+    AT acc[QA_MAXN];
 #pragma unroll
-    for (int k = 0; k < QA_MAXN; ++k) poly[k] = from_d<T>(0.0);
+    for (int k = 0; k < QA_MAXN; ++k) acc[k] = acc_zero((AT*)nullptr);
     const DevBlock* blocks = reinterpret_cast<const DevBlock*>(img + tb.hdr_off);
     const double* coefs = reinterpret_cast<const double*>(img + tb.coef_off);
     for (int bi = 0; bi < tb.nblocks; ++bi) {
@@ -236,10 +241,10 @@ QA_HD void eval_table(const uint8_t* __restrict__ img, const DevTable& tb, LV<S>
         T ws = w * s;
 #pragma unroll
         for (int kk = 0; kk < QA_MAXN; ++kk)
-            if (kk == k) poly[kk] = poly[kk] + ws;
+            if (kk == k) acc_add(acc[kk], ws);
     }
 #pragma unroll
-    for (int k = 0; k < QA_MAXN; ++k) poly[k] = poly[k] * tb.scale;
+    for (int k = 0; k < QA_MAXN; ++k) poly[k] = div_den(acc_get(acc[k]), tb.denom);
 }
 
 template <class T> QA_HD void poly_mul(T* a, const T* b, int n) {
@@ -286,9 +291,12 @@ QA_HD T eval_point(const uint8_t* __restrict__ img, const DevGraph& G, CLV<doubl
         T top[QA_MAXN];
         for (int pi = 0; pi < tm.npieces; ++pi) {
             const DevPiece& pc = pcs[pi];
-            S Us, Vs;
+            DD Ud, Vd;
             double cond;
-            geometry<S>(pc, z, vars, Us, Vs, cond);
+            geometry<S>(pc, z, vars, Ud, Vd, cond);
+            S Us, Vs;
+            store_geo(Us, Ud);
+            store_geo(Vs, Vd);
             T U = lift_to<T>(Us), V = lift_to<T>(Vs);
             cond_max = fmax(cond_max, cond);
             pref = pref * (from_d<T>(1.0) / (U * U));
@@ -297,7 +305,9 @@ QA_HD T eval_point(const uint8_t* __restrict__ img, const DevGraph& G, CLV<doubl
             const int nop = pc.op == QA_OP_US ? 2 : 1;
             const DevTable* tabs = reinterpret_cast<const DevTable*>(img + pc.tab_off);
             T res[2][QA_MAXN];
-            for (int opv = 0; opv < nop; ++opv) {
+#pragma unroll
+            for (int opv = 0; opv < 2; ++opv) {
+                if (opv >= nop) break;
                 T acc[QA_MAXN];
 #pragma unroll
                 for (int k = 0; k < QA_MAXN; ++k) acc[k] = from_d<T>(0.0);
@@ -327,9 +337,11 @@ QA_HD T eval_point(const uint8_t* __restrict__ img, const DevGraph& G, CLV<doubl
 #pragma unroll
                 for (int k = 0; k < QA_MAXN; ++k) top[k] = res[0][k];
             } else {
-                for (int opv = 0; opv < nop; ++opv)
 #pragma unroll
-                    for (int k = 0; k < QA_MAXN; ++k) polys[(pc.out_slot + opv) * QA_MAXN + k] = res[opv][k];
+                for (int opv = 0; opv < 2; ++opv)
+                    if (opv < nop)
+#pragma unroll
+                        for (int k = 0; k < QA_MAXN; ++k) polys[(pc.out_slot + opv) * QA_MAXN + k] = res[opv][k];
             }
         }
         // sum_K top[K] (-1/2)^K Gamma(n-K) Vt^(K-n)

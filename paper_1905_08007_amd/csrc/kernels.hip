@@ -55,7 +55,7 @@ struct Stream {
 // sector-tree sampling from eq. (1): choose j_1..j_M with P(j | S) =
 // W(S\j) / sum_j' W(S\j'), then t_l ~ Exp(Deg(S_l)) and ln z_{j_l} = -sum t.
 // Writes z (normalised) through zv, returns log p; order[l] = j_(l+1).
-__device__ bool sample_point(const double* __restrict__ D, const double* __restrict__ W, int M, const Stream& st,
+__device__ __forceinline__ bool sample_point(const double* __restrict__ D, const double* __restrict__ W, int M, const Stream& st,
                              LV<double> zv, double& logp, uint8_t* order, double* tl) {
     const uint32_t full = (1u << M) - 1;
     uint32_t S = full;
@@ -162,8 +162,13 @@ template <class T> __host__ __device__ size_t lds_bytes_dev(int npoly, int nt) {
 }
 template <class T> size_t lds_bytes(int npoly, int nt) { return lds_bytes_dev<T>(npoly, nt); }
 
+// Running error bound: the graph polynomials are computed in double-double and
+// rounded (relative error <= u), the coefficient tables are exact integers, so
+// the FP64 result differs from the exact value by at most C u mag, where mag is
+// the same computation carried out on magnitudes and C = 128 exceeds the
+// number of roundings along any product / sum path of the evaluation.
 constexpr double QA_U = 0x1p-53;
-__device__ __forceinline__ double bound_of(double mag, double cond) { return mag * QA_U * (64.0 + 12.0 * cond); }
+__device__ __forceinline__ double bound_of(double mag, double) { return mag * QA_U * 128.0; }
 
 __global__ void __launch_bounds__(64) k_eval_fp64(const uint8_t* __restrict__ img, uint32_t graph,
                                                   const double* __restrict__ z, uint64_t count, double* __restrict__ f) {
@@ -202,12 +207,20 @@ __global__ void __launch_bounds__(64) k_eval_dd(const uint8_t* __restrict__ img,
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const DevGraph& G = dev_graph(img, graph);
+    double cond;
+    double mag = 0.0;
+    if (err) {   // magnitude pass for the bound
+        LV<double> v1;
+        LV<EB> p1;
+        lane_views<EB>(lds, G.npoly, v1, p1);
+        mag = eval_point<EB>(img, G, CLV<double>{z + i, (int)count}, v1, p1, cond).a;
+    }
     LV<DD> vars, polys;
     lane_views<DD>(lds, G.npoly, vars, polys);
-    double cond;
     DD r = eval_point<DD>(img, G, CLV<double>{z + i, (int)count}, vars, polys, cond);
     f[i] = r.hi + r.lo;
-    if (err) err[i] = fabs(r.hi) * 0x1p-100 * (64.0 + 12.0 * cond * cond) + fabs(r.lo) * 0x1p-53;
+    // double-double roundings (u^2 scale) on the same paths, plus the final rounding to double
+    if (err) err[i] = mag * 0x1p-104 * 256.0 + fabs(r.hi + r.lo) * QA_U;
 }
 
 // ---------------------------------------------------------------------------
@@ -288,6 +301,7 @@ struct Work {
     double* zbuf;            // per persistent wave: QA_MAXM * 64
     uint32_t tile, per_round, ng;
     uint64_t ntiles;
+    uint64_t first;
 };
 
 __device__ __forceinline__ void tile_of(const Work& w, uint64_t gt, uint32_t& g, uint64_t& s0, uint32_t& cnt) {
@@ -297,9 +311,10 @@ __device__ __forceinline__ void tile_of(const Work& w, uint64_t gt, uint32_t& g,
         if (w.gtile0[mid] <= gt) lo = mid; else hi = mid;
     }
     g = lo;
-    s0 = (gt - w.gtile0[lo]) * w.tile;
-    const uint64_t rem = w.budget[lo] - s0;
+    const uint64_t off = (gt - w.gtile0[lo]) * w.tile;
+    const uint64_t rem = w.budget[lo] - off;
     cnt = (uint32_t)(rem < w.tile ? rem : w.tile);
+    s0 = w.first + off;
 }
 
 __global__ void k_reset(Work w) {
@@ -541,8 +556,8 @@ extern "C" int qa_sample_pdf(const void* dev, uint32_t graph, uint64_t seed, uin
     auto* img = image_of(dev);
     if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
     if (!host_graph(*img, graph)) return qa_fail(QA_EINVAL, "graph index out of range");
-    if (!z || !logp) return qa_fail(QA_EINVAL, "NULL output");
     if (count == 0) return QA_OK;
+    if (!z || !logp) return qa_fail(QA_EINVAL, "NULL output");
     if (count > (1ull << 31)) return qa_fail(QA_EINVAL, "count too large for one call");
     const uint2 key = make_uint2((uint32_t)seed, tag);
     dim3 grid((unsigned)((count + 255) / 256));
@@ -558,8 +573,8 @@ extern "C" int qa_eval_integrand(const void* dev, uint32_t graph, const double* 
     if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
     const DevGraph* G = host_graph(*img, graph);
     if (!G) return qa_fail(QA_EINVAL, "graph index out of range");
-    if (!z || !f) return qa_fail(QA_EINVAL, "NULL argument");
     if (count == 0) return QA_OK;
+    if (!z || !f) return qa_fail(QA_EINVAL, "NULL argument");
     if (count > (1ull << 31)) return qa_fail(QA_EINVAL, "count too large for one call");
     dim3 grid((unsigned)((count + 63) / 64)), block(64);
     const uint8_t* d = (const uint8_t*)dev;
@@ -583,8 +598,8 @@ extern "C" int qa_eval_integrand(const void* dev, uint32_t graph, const double* 
 }
 
 extern "C" int qa_accumulate(const double* f, const double* logp, uint64_t count, qa_acc* acc, void* stream) {
-    if (!f || !logp || !acc) return qa_fail(QA_EINVAL, "NULL argument");
     if (count == 0) return QA_OK;
+    if (!f || !logp || !acc) return qa_fail(QA_EINVAL, "NULL argument");
     hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(1024), 0, (hipStream_t)stream, f, logp, count, acc);
     HIPCHK(hipGetLastError());
     return QA_OK;
@@ -630,8 +645,9 @@ extern "C" int qa_work_bytes(const qa_set* s, const uint64_t* budgets, uint32_t 
     return QA_OK;
 }
 
-extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t seed, uint32_t tag,
-                            uint32_t tile, uint32_t grid, void* work, size_t work_bytes, qa_acc* acc, void* stream) {
+extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t first, uint64_t seed,
+                            uint32_t tag, uint32_t tile, uint32_t grid, void* work, size_t work_bytes, qa_acc* acc,
+                            double* fused_ms, void* stream) {
     auto* img = image_of(dev);
     if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
     if (!s || !budgets || !work || !acc) return qa_fail(QA_EINVAL, "NULL argument");
@@ -667,6 +683,7 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     w.per_round = kPerRound;
     w.ng = (uint32_t)ng;
     w.ntiles = ntiles;
+    w.first = first;
     const uint2 key = make_uint2((uint32_t)seed, tag);
     int maxpoly = 1;
     for (size_t g = 0; g < ng; ++g) maxpoly = std::max(maxpoly, host_graph(*img, (uint32_t)g)->npoly);
@@ -675,27 +692,49 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     if (int rc = lds_attr(k_fused, lds_fp)) return rc;
     if (int rc = lds_attr(k_fix_dd, lds_dd)) return rc;
     // one round as a graph: reset queue, fused pass, double-double pass, reduce, advance
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (fused_ms) {
+        *fused_ms = 0.0;
+        HIPCHK(hipEventCreate(&ev0));
+        HIPCHK(hipEventCreate(&ev1));
+    }
+    // the graph is captured on a private stream (capture is not allowed on
+    // the null stream) and replayed on the caller's stream
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipGraph_t graph;
     hipGraphExec_t exec;
-    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, w);
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(64), lds_fp, st, (const uint8_t*)dev, key, w);
-    hipLaunchKernelGGL(k_fix_dd, dim3(grid), dim3(64), lds_dd, st, (const uint8_t*)dev, key, w);
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, st, w, acc);
-    hipLaunchKernelGGL(k_next_round, dim3(1), dim3(64), 0, st, w);
-    HIPCHK(hipStreamEndCapture(st, &graph));
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, cs, w);
+    if (ev0) hipEventRecord(ev0, cs);
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(64), lds_fp, cs, (const uint8_t*)dev, key, w);
+    if (ev1) hipEventRecord(ev1, cs);
+    hipLaunchKernelGGL(k_fix_dd, dim3(grid), dim3(64), lds_dd, cs, (const uint8_t*)dev, key, w);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, cs, w, acc);
+    hipLaunchKernelGGL(k_next_round, dim3(1), dim3(64), 0, cs, w);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    hipStreamDestroy(cs);
+    if (ce != hipSuccess) return qa_fail(QA_EHIP, std::string("capture: ") + hipGetErrorString(ce));
     HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    for (uint64_t r = 0; r < rounds; ++r) {
+    int rc = QA_OK;
+    for (uint64_t r = 0; r < rounds && rc == QA_OK; ++r) {
         hipError_t e = hipGraphLaunch(exec, st);
-        if (e != hipSuccess) {
-            hipGraphExecDestroy(exec);
-            hipGraphDestroy(graph);
-            return qa_fail(QA_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        if (e != hipSuccess) { rc = qa_fail(QA_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e)); break; }
+        if (fused_ms) {
+            e = hipEventSynchronize(ev1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+            if (e != hipSuccess) { rc = qa_fail(QA_EHIP, std::string("event timing: ") + hipGetErrorString(e)); break; }
+            *fused_ms += ms;
         }
     }
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipGraphExecDestroy(exec));
-    HIPCHK(hipGraphDestroy(graph));
+    hipError_t e = hipStreamSynchronize(st);
+    hipGraphExecDestroy(exec);
+    hipGraphDestroy(graph);
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+    if (rc != QA_OK) return rc;
+    if (e != hipSuccess) return qa_fail(QA_EHIP, std::string("integrate: ") + hipGetErrorString(e));
     return QA_OK;
 }
 
@@ -705,8 +744,8 @@ extern "C" int qa_variance_grad(const void* dev, uint32_t graph, uint64_t seed, 
     if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
     const DevGraph* G = host_graph(*img, graph);
     if (!G) return qa_fail(QA_EINVAL, "graph index out of range");
-    if (!grad || !w2sum) return qa_fail(QA_EINVAL, "NULL argument");
     if (count == 0) return QA_OK;
+    if (!grad || !w2sum) return qa_fail(QA_EINVAL, "NULL argument");
     if (count > (1ull << 31)) return qa_fail(QA_EINVAL, "count too large for one call");
     const unsigned nb = (unsigned)((count + 63) / 64);
     if (int rc = lds_attr(k_vargrad, lds_bytes<double>(G->npoly, 64) + 8 * QA_MAXM * 64)) return rc;

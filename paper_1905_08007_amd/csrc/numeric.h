@@ -28,28 +28,41 @@ QA_HD double fma_(double a, double b, double c) { return fma(a, b, c); }
 QA_HD double val(double x) { return x; }
 QA_HD double mag(double x) { return fabs(x); }
 
-// ---- double-double (Dekker / Knuth error-free transformations)
+// ---- double-double (Dekker / Knuth error-free transformations).  Floating
+// point contraction is switched off inside these primitives: fusing the
+// product of two_prod into the next addition would break the error-free
+// transformations.
 struct DD {
     double hi, lo;
 };
 QA_HD DD two_sum(double a, double b) {
+#pragma clang fp contract(off)
+
     double s = a + b;
     double bb = s - a;
     double e = (a - (s - bb)) + (b - bb);
     return DD{s, e};
 }
 QA_HD DD quick_two_sum(double a, double b) {
+#pragma clang fp contract(off)
+
     double s = a + b;
     double e = b - (s - a);
     return DD{s, e};
 }
 QA_HD DD two_prod(double a, double b) {
+#pragma clang fp contract(off)
+
     double p = a * b;
     double e = fma(a, b, -p);
     return DD{p, e};
 }
-QA_HD DD dd(double x) { return DD{x, 0.0}; }
+QA_HD DD dd(double x) {
+#pragma clang fp contract(off)
+ return DD{x, 0.0}; }
 QA_HD DD operator+(DD a, DD b) {
+#pragma clang fp contract(off)
+
     DD s = two_sum(a.hi, b.hi);
     DD t = two_sum(a.lo, b.lo);
     s.lo += t.hi;
@@ -57,19 +70,29 @@ QA_HD DD operator+(DD a, DD b) {
     s.lo += t.lo;
     return quick_two_sum(s.hi, s.lo);
 }
-QA_HD DD operator-(DD a) { return DD{-a.hi, -a.lo}; }
-QA_HD DD operator-(DD a, DD b) { return a + (-b); }
+QA_HD DD operator-(DD a) {
+#pragma clang fp contract(off)
+ return DD{-a.hi, -a.lo}; }
+QA_HD DD operator-(DD a, DD b) {
+#pragma clang fp contract(off)
+ return a + (-b); }
 QA_HD DD operator*(DD a, DD b) {
+#pragma clang fp contract(off)
+
     DD p = two_prod(a.hi, b.hi);
     p.lo += a.hi * b.lo + a.lo * b.hi;
     return quick_two_sum(p.hi, p.lo);
 }
 QA_HD DD operator*(DD a, double c) {
+#pragma clang fp contract(off)
+
     DD p = two_prod(a.hi, c);
     p.lo += a.lo * c;
     return quick_two_sum(p.hi, p.lo);
 }
 QA_HD DD operator/(DD a, DD b) {
+#pragma clang fp contract(off)
+
     double q1 = a.hi / b.hi;
     DD r = a - b * q1;
     double q2 = r.hi / b.hi;
@@ -78,23 +101,74 @@ QA_HD DD operator/(DD a, DD b) {
     DD q = quick_two_sum(q1, q2);
     return q + dd(q3);
 }
-QA_HD DD& operator+=(DD& x, DD y) { x = x + y; return x; }
-QA_HD DD& operator*=(DD& x, DD y) { x = x * y; return x; }
-QA_HD DD fma_(DD a, DD b, DD c) { return a * b + c; }
-QA_HD double val(DD x) { return x.hi + x.lo; }
-QA_HD double mag(DD x) { return fabs(x.hi); }
+QA_HD DD& operator+=(DD& x, DD y) {
+#pragma clang fp contract(off)
+ x = x + y; return x; }
+QA_HD DD& operator*=(DD& x, DD y) {
+#pragma clang fp contract(off)
+ x = x * y; return x; }
+QA_HD DD fma_(DD a, DD b, DD c) {
+#pragma clang fp contract(off)
+ return a * b + c; }
+QA_HD double val(DD x) {
+#pragma clang fp contract(off)
+ return x.hi + x.lo; }
+QA_HD double mag(DD x) {
+#pragma clang fp contract(off)
+ return fabs(x.hi); }
 QA_HD DD sqrt_(DD a) {
+#pragma clang fp contract(off)
+
     double x = sqrt(a.hi);
     DD r = a - two_prod(x, x);
     return quick_two_sum(x, r.hi / (2.0 * x));
 }
-QA_HD double sqrt_(double a) { return sqrt(a); }
-QA_HD DD operator/(DD a, double b) { return a / dd(b); }
+QA_HD double sqrt_(double a) {
+#pragma clang fp contract(off)
+ return sqrt(a); }
+QA_HD DD operator/(DD a, double b) {
+#pragma clang fp contract(off)
+ return a / dd(b); }
+
+QA_HD DD operator/(DD a, int b) {
+#pragma clang fp contract(off)
+ return a / dd((double)b); }
+QA_HD double to_d(DD x) {
+#pragma clang fp contract(off)
+ return x.hi + x.lo; }
 
 template <class T> QA_HD T from_d(double x);
-// geometry storage type of an evaluation type, and the lift from storage
+// storage type of the geometry variables for an evaluation type (the
+// geometry itself is always computed in double-double), and the lift
 template <class T> struct GeoOf { using type = double; };
 template <> struct GeoOf<DD> { using type = DD; };
+QA_HD void store_geo(double& dst, DD x) { dst = x.hi + x.lo; }
+QA_HD void store_geo(DD& dst, DD x) { dst = x; }
+
+// block accumulators: plain, value in double-double with magnitude, double-double
+template <class T> struct Acc { using type = T; };
+struct EBAcc {
+    DD v;
+    double a;
+};
+template <> struct Acc<EB> { using type = EBAcc; };
+QA_HD double acc_zero(double*) { return 0.0; }
+QA_HD EBAcc acc_zero(EBAcc*) { return EBAcc{DD{0.0, 0.0}, 0.0}; }
+QA_HD DD acc_zero(DD*) { return DD{0.0, 0.0}; }
+QA_HD void acc_add(double& s, double x) { s += x; }
+QA_HD void acc_add(EBAcc& s, EB x) {
+#pragma clang fp contract(off)
+    s.v = s.v + dd(x.v);
+    s.a += x.a;
+}
+QA_HD void acc_add(DD& s, DD x) { s = s + x; }
+QA_HD double acc_get(double s) { return s; }
+QA_HD EB acc_get(EBAcc s) { return EB{s.v.hi + s.v.lo, s.a}; }
+QA_HD DD acc_get(DD s) { return s; }
+// division by the exact integer denominator of a table
+QA_HD double div_den(double x, double d) { return x / d; }
+QA_HD EB div_den(EB x, double d) { return EB{x.v / d, x.a / d}; }
+QA_HD DD div_den(DD x, double d) { return x / dd(d); }
 QA_HD double lift(double x, double*) { return x; }
 QA_HD EB lift(double x, EB*) { return EB{x, fabs(x)}; }
 QA_HD DD lift(DD x, DD*) { return x; }

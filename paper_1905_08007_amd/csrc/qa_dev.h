@@ -49,7 +49,7 @@ struct DevPiece {
 struct DevTable {
     int32_t nblocks;
     int32_t has_q;                         // Gamma_1 part present (A projector)
-    double scale;                          // 1 / common denominator of the coefficients
+    double denom;                          // common denominator of the integer coefficients
     uint64_t hdr_off;                      // DevBlock[nblocks], sorted by k
     uint64_t coef_off;                     // double coefficients, blocks back to back
 };
