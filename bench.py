@@ -112,7 +112,7 @@ def main():
     dt = time.perf_counter() - t0
 
     # per-graph sums over the timed steps
-    tot = np.zeros(ng, dtype=[("n", "f8"), ("s1", "f8"), ("s2", "f8"), ("flag", "f8"), ("bad", "f8")])
+    tot = np.zeros(ng, dtype=[("n", "f8"), ("s1", "f8"), ("s2", "f8"), ("flag", "f8"), ("bad", "f8"), ("res", "f8")])
     for acc in accs:
         a = P.read_acc(acc)
         tot["n"] += a["n"]
@@ -120,6 +120,7 @@ def main():
         tot["s2"] += a["s2_hi"] + a["s2_lo"]
         tot["flag"] += a["n_flagged"]
         tot["bad"] += a["n_bad"]
+        tot["res"] += a["n_residual"]
     val, var = 0.0, 0.0
     for i, g in enumerate(graphs):
         n = tot["n"][i]
@@ -163,6 +164,7 @@ def main():
             "class_sigma": sigma,
             "flagged_fraction": float(tot["flag"].sum() / max(1.0, tot["n"].sum())),
             "bad_points": int(tot["bad"].sum()),
+            "residual_points": int(tot["res"].sum()),
             "host_setup_s": setup_s,
             "fused_kernel_ms_per_step": fused_ms / args.steps,
             "eval_flops_per_sample": eval_flops_step / (per * ng),

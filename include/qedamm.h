@@ -49,6 +49,7 @@ typedef struct qa_acc {
     double s2_hi, s2_lo;
     uint64_t n_flagged;   /* points recomputed in double-double */
     uint64_t n_bad;       /* non-finite or underflowed points, excluded */
+    uint64_t n_residual;  /* flagged points whose double-double bound still exceeds 1e-10 |f| (kept, counted) */
 } qa_acc;
 
 typedef struct qa_set qa_set;   /* graphs + forests + integrand tables (host) */
@@ -124,7 +125,9 @@ int qa_sample_pdf(const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, 
  * scale: f is homogeneous of degree -M and is evaluated at z / sum z).
  * mode QA_FP64: f only.  QA_FP64_BOUND: also err[i] = running error bound and
  * flag[i] = 1 if err > 1e-11 |f|.  QA_DD: double-double evaluation, err = its
- * bound.  err and flag may be NULL for QA_FP64.  Units: (alpha/pi)^n. */
+ * bound (when err is non-NULL an FP64 magnitude pass runs first to form it).
+ * The bounds include the conditioning of the graph polynomials (computed in
+ * double-double in every mode).  err and flag may be NULL for QA_FP64.  Units: (alpha/pi)^n. */
 int qa_eval_integrand(const void* dev, uint32_t graph, const double* z, uint64_t count, int mode,
                       double* f, double* err, uint8_t* flag, void* stream);
 

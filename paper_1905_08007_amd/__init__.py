@@ -26,8 +26,8 @@ class QaGraph(C.Structure):
 
 
 ACC_DTYPE = np.dtype([("n", "<u8"), ("s1_hi", "<f8"), ("s1_lo", "<f8"), ("s2_hi", "<f8"),
-                      ("s2_lo", "<f8"), ("n_flagged", "<u8"), ("n_bad", "<u8")])
-ACC_BYTES = ACC_DTYPE.itemsize  # 56
+                      ("s2_lo", "<f8"), ("n_flagged", "<u8"), ("n_bad", "<u8"), ("n_residual", "<u8")])
+ACC_BYTES = ACC_DTYPE.itemsize  # 64
 
 _lib = None
 

@@ -392,6 +392,13 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
                     uint64_t coff = P.alloc(8 * std::max<size_t>(1, ncoef), 256);
                     DevTable dtb{};
                     dtb.nblocks = (int)tb.blocks.size();
+                    for (int k = 0, bi = 0; k <= QA_MAXN; ++k) {
+                        while (bi < dtb.nblocks && tb.blocks[bi].k < k) ++bi;
+                        dtb.kstart[k] = bi;
+                    }
+                    for (size_t bi = 1; bi < tb.blocks.size(); ++bi)
+                        if (tb.blocks[bi].k == tb.blocks[bi - 1].k && tb.blocks[bi].r != tb.blocks[bi - 1].r)
+                            throw std::runtime_error("blocks of one k must share r");
                     dtb.has_q = tb.has_q;
                     dtb.denom = 1.0 / tb.scale;
                     dtb.hdr_off = hoff;

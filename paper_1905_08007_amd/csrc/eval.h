@@ -70,7 +70,7 @@ QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& 
             }
         }
     }
-    cond = dmax / dmin;
+    cond = dmax / dmin;   // loop-matrix conditioning proxy (largest diagonal / smallest pivot)
     U = from_d<T>(1.0);
 #pragma unroll
     for (int c = 0; c < L; ++c) U = U * (R[c][c] * R[c][c]);
@@ -127,6 +127,13 @@ QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& 
         for (int c = 0; c < L; ++c)
             if (in[i][c]) { a = a - y[c]; cq = cq - yq[c]; }
         if (!hq) cq = from_d<T>(0.0);
+        // cancellation ratios of the flows (magnitude / value), for the error bounds
+        double ma = 1.0, mc = hq ? 0.5 : 0.0;
+#pragma unroll
+        for (int c = 0; c < L; ++c)
+            if (in[i][c]) { ma += fabs(val(y[c])); mc += fabs(val(yq[c])); }
+        cond = fmax(cond, ma / fabs(val(a)));
+        if (hq) cond = fmax(cond, mc / fabs(val(cq)));
         store_geo(vars[QA_VAR_A + i], a);
         store_geo(vars[QA_VAR_C + i], cq);
         V = V + zl[i] * (from_d<T>(1.0) - a);
@@ -146,9 +153,11 @@ QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& 
         for (int j = i; j < QA_MAXL; ++j) {
             if (j < nl) {
                 T s = from_d<T>(0.0);
+                double ms = 0.0;
 #pragma unroll
                 for (int d = 0; d < L; ++d)
-                    if (in[j][d]) s = s + Y[i][d];
+                    if (in[j][d]) { s = s + Y[i][d]; ms += fabs(val(Y[i][d])); }
+                cond = fmax(cond, ms / fabs(val(s)));
                 store_geo(vars[tri_idx(i, j)], s);
             }
         }
@@ -167,23 +176,27 @@ QA_HD void geometry(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V,
 }
 
 // ---------------------------------------------------------------------------
-// multilinear fold: sum_s c[s] prod_{bit i of s} A[i], r <= QA_MAXR
-template <class T, int R> struct Fold {
+// multilinear fold: sum_s c[s] prod_{bit i of s} A[map(i)], r <= QA_MAXR, where
+// map skips the compile-time index J (J = QA_MAXR: no skip).  Used with the
+// free-slot values A of a block; the q-derivative part folds the other slots.
+template <int J> QA_HD constexpr int amap(int i) { return i + (i >= J ? 1 : 0); }
+
+template <class T, int R, int J> struct Fold {
     QA_HD static T run(const double* c, const T* A) {
-        return Fold<T, R - 1>::run(c, A) + A[R - 1] * Fold<T, R - 1>::run(c + (1 << (R - 1)), A);
+        return Fold<T, R - 1, J>::run(c, A) + A[amap<J>(R - 1)] * Fold<T, R - 1, J>::run(c + (1 << (R - 1)), A);
     }
 };
-template <class T> struct Fold<T, 0> {
+template <class T, int J> struct Fold<T, 0, J> {
     QA_HD static T run(const double* c, const T*) { return from_d<T>(c[0]); }
 };
 
-template <class T> QA_HD T fold(const double* c, const T* A, int r) {
+template <class T, int J> QA_HD T fold(const double* c, const T* A, int r) {
     switch (r) {
-        case 0: return Fold<T, 0>::run(c, A);
-        case 1: return Fold<T, 1>::run(c, A);
-        case 2: return Fold<T, 2>::run(c, A);
-        case 3: return Fold<T, 3>::run(c, A);
-        case 4: return Fold<T, 4>::run(c, A);
+        case 0: return Fold<T, 0, J>::run(c, A);
+        case 1: return Fold<T, 1, J>::run(c, A);
+        case 2: return Fold<T, 2, J>::run(c, A);
+        case 3: return Fold<T, 3, J>::run(c, A);
+        case 4: return Fold<T, 4, J>::run(c, A);
         default: break;
     }
     // 16-coefficient leaves combined by a carry chain over the high bits
@@ -191,60 +204,124 @@ template <class T> QA_HD T fold(const double* c, const T* A, int r) {
     T v = from_d<T>(0.0);
     const int nleaves = 1 << (r - 4);
     for (int leaf = 0; leaf < nleaves; ++leaf) {
-        v = Fold<T, 4>::run(c + 16 * leaf, A);
+        v = Fold<T, 4, J>::run(c + 16 * leaf, A);
         int b = leaf;
         bool stored = false;
 #pragma unroll
         for (int l = 0; l < QA_MAXR - 4; ++l) {
             if (stored || 4 + l >= r) break;
             if ((b & 1) == 0) { acc[l] = v; stored = true; }
-            else { v = acc[l] + A[4 + l] * v; b >>= 1; }
+            else { v = acc[l] + A[amap<J>(4 + l)] * v; b >>= 1; }
         }
     }
     return v;
 }
 
-// Evaluate one coefficient table: poly[k] = scale * sum over blocks with k pairs
+// sum over the free slot j carrying the q-derivative: C_j * fold(others)
+template <class T, class S, int J> struct QTerms {
+    QA_HD static void run(T& s, const double* c, const T* A, int r, LV<S> vars, const DevBlock& b) {
+        if (J >= r) return;
+        const int half = 1 << (r - 1);
+        s = s + lift_to<T>(vars[b.cidx[J]]) * fold<T, J>(c + (1 << r) + J * half, A, r - 1);
+        QTerms<T, S, J + 1>::run(s, c, A, r, vars, b);
+    }
+};
+template <class T, class S> struct QTerms<T, S, QA_MAXR> {
+    QA_HD static void run(T&, const double*, const T*, int, LV<S>, const DevBlock&) {}
+};
+
+// one block: w * (Gamma_0 fold + Gamma_1 folds)
+template <class T, class S>
+QA_HD T eval_block(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
+    const int k = b.k, r = b.r;
+    T w = from_d<T>(1.0);
+#pragma unroll
+    for (int q = 0; q < QA_MAXK; ++q)
+        if (q < k) w = w * lift_to<T>(vars[b.bidx[q]]);
+    T A[QA_MAXR + 1];
+#pragma unroll
+    for (int i = 0; i < QA_MAXR; ++i) A[i] = i < r ? lift_to<T>(vars[b.aidx[i]]) : from_d<T>(0.0);
+    A[QA_MAXR] = from_d<T>(0.0);
+    T s = fold<T, QA_MAXR>(c, A, r);
+    if (has_q) QTerms<T, S, 0>::run(s, c, A, r, vars, b);
+    return w * s;
+}
+
+// statically sized block (R free slots, R <= QA_STATIC_R): fully unrolled folds
+#define QA_STATIC_R 6
+template <class T, class S, int R, int J> struct QStatic {
+    QA_HD static void run(T& s, const double* c, const T* A, LV<S> vars, const DevBlock& b) {
+        s = s + lift_to<T>(vars[b.cidx[J]]) * Fold<T, R - 1, J>::run(c + (1 << R) + J * (1 << (R - 1)), A);
+        QStatic<T, S, R, J + 1>::run(s, c, A, vars, b);
+    }
+};
+template <class T, class S, int R> struct QStatic<T, S, R, R> {
+    QA_HD static void run(T&, const double*, const T*, LV<S>, const DevBlock&) {}
+};
+
+template <class T, class S, int R>
+QA_HD T block_static(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
+    const int k = b.k;
+    T w = from_d<T>(1.0);
+#pragma unroll
+    for (int q = 0; q < QA_MAXK; ++q)
+        if (q < k) w = w * lift_to<T>(vars[b.bidx[q]]);
+    T A[R + 1];
+#pragma unroll
+    for (int i = 0; i < R; ++i) A[i] = lift_to<T>(vars[b.aidx[i]]);
+    A[R] = from_d<T>(0.0);
+    T s = Fold<T, R, QA_MAXR>::run(c, A);
+    if (has_q) QStatic<T, S, R, 0>::run(s, c, A, vars, b);
+    return w * s;
+}
+
+// blocks [b0, b1) all with R free slots, two at a time for instruction-level parallelism
+template <class T, class S, int R, class AT>
+QA_HD void group_static(const DevBlock* blocks, int b0, int b1, const double* coefs, LV<S> vars, bool hq, AT& acc) {
+    int bi = b0;
+    for (; bi + 1 < b1; bi += 2) {
+        const DevBlock& x = blocks[bi];
+        const DevBlock& y = blocks[bi + 1];
+        const T vx = block_static<T, S, R>(x, coefs + x.coef, vars, hq);
+        const T vy = block_static<T, S, R>(y, coefs + y.coef, vars, hq);
+        acc_add(acc, vx);
+        acc_add(acc, vy);
+    }
+    if (bi < b1) acc_add(acc, block_static<T, S, R>(blocks[bi], coefs + blocks[bi].coef, vars, hq));
+}
+
+// Evaluate one coefficient table: poly[k] = (1/denom) * sum over blocks with k
+// pairs.  All blocks with the same k have the same number of free slots r.
 template <class T, class S>
 QA_HD void eval_table(const uint8_t* __restrict__ img, const DevTable& tb, LV<S> vars, int n, T* poly) {
     using AT = typename Acc<T>::type;
-    AT acc[QA_MAXN];
-#pragma unroll
-    for (int k = 0; k < QA_MAXN; ++k) acc[k] = acc_zero((AT*)nullptr);
     const DevBlock* blocks = reinterpret_cast<const DevBlock*>(img + tb.hdr_off);
     const double* coefs = reinterpret_cast<const double*>(img + tb.coef_off);
-    for (int bi = 0; bi < tb.nblocks; ++bi) {
-        const DevBlock& b = blocks[bi];
-        const int k = b.k, r = b.r;
-        if (k >= n) break;
-        T w = from_d<T>(1.0);
+    const bool hq = tb.has_q != 0;
 #pragma unroll
-        for (int q = 0; q < QA_MAXK; ++q)
-            if (q < k) w = w * lift_to<T>(vars[b.bidx[q]]);
-        T A[QA_MAXR];
-#pragma unroll
-        for (int i = 0; i < QA_MAXR; ++i) A[i] = i < r ? lift_to<T>(vars[b.aidx[i]]) : from_d<T>(0.0);
-        const double* c = coefs + b.coef;
-        T s = fold(c, A, r);
-        if (tb.has_q) {
-            const int half = r > 0 ? 1 << (r - 1) : 0;
-#pragma unroll
-            for (int j = 0; j < QA_MAXR; ++j) {
-                if (j >= r) break;
-                T Ap[QA_MAXR];
-#pragma unroll
-                for (int i = 0; i < QA_MAXR - 1; ++i) Ap[i] = i < j ? A[i] : A[i + 1];
-                Ap[QA_MAXR - 1] = from_d<T>(0.0);
-                s = s + lift_to<T>(vars[b.cidx[j]]) * fold(c + (1 << r) + j * half, Ap, r - 1);
+    for (int k = 0; k < QA_MAXN; ++k) {
+        AT acc = acc_zero((AT*)nullptr);
+        const int b0 = tb.kstart[k], b1 = tb.kstart[k + 1];
+        if (k < n && b0 < b1) {
+            // the double-double path (flagged points only) uses the compact generic loop
+            const int rsel = sizeof(T) == sizeof(DD) && sizeof(S) == sizeof(DD) ? -1 : blocks[b0].r;
+            switch (rsel) {
+                case 0: group_static<T, S, 0>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 1: group_static<T, S, 1>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 2: group_static<T, S, 2>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 3: group_static<T, S, 3>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 4: group_static<T, S, 4>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 5: group_static<T, S, 5>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 6: group_static<T, S, 6>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                default:
+                    for (int bi = b0; bi < b1; ++bi) {
+                        const DevBlock& b = blocks[bi];
+                        acc_add(acc, eval_block<T, S>(b, coefs + b.coef, vars, hq));
+                    }
             }
         }
-        T ws = w * s;
-#pragma unroll
-        for (int kk = 0; kk < QA_MAXN; ++kk)
-            if (kk == k) acc_add(acc[kk], ws);
+        poly[k] = div_den(acc_get(acc), tb.denom);
     }
-#pragma unroll
-    for (int k = 0; k < QA_MAXN; ++k) poly[k] = div_den(acc_get(acc[k]), tb.denom);
 }
 
 template <class T> QA_HD void poly_mul(T* a, const T* b, int n) {
@@ -269,10 +346,12 @@ QA_HD double kcoef(int n, int K) {
     return g * h;
 }
 
-// f_G(z) at one point.  z: the M line parameters (any positive scale; they
-// are used as given, so callers normalise to sum 1).  Returns f; for EB the
-// magnitude carries the rounding-error scale; cond_out = worst loop-matrix
-// conditioning seen.
+// f_G(z) at one point.  z: the M line parameters, used as given (f is
+// homogeneous of degree -M).  Returns f; for EB the magnitude carries the
+// rounding-error scale; cond_out = worst conditioning of the graph
+// polynomials seen (loop-matrix pivot ratio, cancellation ratios of flows and
+// contraction coefficients), which bounds their relative error in units of
+// the double-double round-off.
 template <class T>
 QA_HD T eval_point(const uint8_t* __restrict__ img, const DevGraph& G, CLV<double> z,
                    LV<typename GeoOf<T>::type> vars, LV<T> polys, double& cond_out) {

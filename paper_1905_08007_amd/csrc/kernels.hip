@@ -162,13 +162,19 @@ template <class T> __host__ __device__ size_t lds_bytes_dev(int npoly, int nt) {
 }
 template <class T> size_t lds_bytes(int npoly, int nt) { return lds_bytes_dev<T>(npoly, nt); }
 
-// Running error bound: the graph polynomials are computed in double-double and
-// rounded (relative error <= u), the coefficient tables are exact integers, so
-// the FP64 result differs from the exact value by at most C u mag, where mag is
-// the same computation carried out on magnitudes and C = 128 exceeds the
-// number of roundings along any product / sum path of the evaluation.
+// Running error bounds.  The graph polynomials are computed in double-double;
+// their relative error is <= 16 * cond * 2^-104 (cond: their conditioning from
+// eval_point).  The coefficient tables are exact integers.  The FP64
+// evaluation then differs from the exact value by at most
+//   u * mag * (128 + 16 * cond * 2^-51),
+// where mag is the same computation on magnitudes and 128 exceeds the number
+// of roundings along any product / sum path; the double-double evaluation by
+//   2^-104 * mag * (256 + 16 * cond) + u |f| (final rounding to double).
 constexpr double QA_U = 0x1p-53;
-__device__ __forceinline__ double bound_of(double mag, double) { return mag * QA_U * 128.0; }
+__device__ __forceinline__ double bound_of(double mag, double cond) { return mag * QA_U * (128.0 + 16.0 * cond * 0x1p-51); }
+__device__ __forceinline__ double bound_dd(double mag, double cond, double f) {
+    return mag * 0x1p-104 * (256.0 + 16.0 * cond) + fabs(f) * QA_U;
+}
 
 __global__ void __launch_bounds__(64) k_eval_fp64(const uint8_t* __restrict__ img, uint32_t graph,
                                                   const double* __restrict__ z, uint64_t count, double* __restrict__ f) {
@@ -207,7 +213,7 @@ __global__ void __launch_bounds__(64) k_eval_dd(const uint8_t* __restrict__ img,
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const DevGraph& G = dev_graph(img, graph);
-    double cond;
+    double cond = 1.0, cond_dd;
     double mag = 0.0;
     if (err) {   // magnitude pass for the bound
         LV<double> v1;
@@ -217,10 +223,9 @@ __global__ void __launch_bounds__(64) k_eval_dd(const uint8_t* __restrict__ img,
     }
     LV<DD> vars, polys;
     lane_views<DD>(lds, G.npoly, vars, polys);
-    DD r = eval_point<DD>(img, G, CLV<double>{z + i, (int)count}, vars, polys, cond);
+    DD r = eval_point<DD>(img, G, CLV<double>{z + i, (int)count}, vars, polys, cond_dd);
     f[i] = r.hi + r.lo;
-    // double-double roundings (u^2 scale) on the same paths, plus the final rounding to double
-    if (err) err[i] = mag * 0x1p-104 * 256.0 + fabs(r.hi + r.lo) * QA_U;
+    if (err) err[i] = bound_dd(mag, fmax(cond, cond_dd), r.hi + r.lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -289,7 +294,9 @@ struct Partial {
 struct FlagEntry {
     uint64_t sample;
     double w;         // FP64 weight
+    double mag, cond; // magnitude and conditioning from the FP64 pass
     double c1, c2;    // corrections written by the double-double pass
+    uint64_t residual;// 1 if the double-double bound still exceeds 1e-10 |f|
 };
 struct Work {
     uint32_t* counter;       // [0] tile queue, [1] round
@@ -355,7 +362,7 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
         for (uint32_t base = 0; base < cnt; base += 64) {
             const uint32_t j = base + lane;
             const bool act = j < cnt;
-            double wv = 0.0;
+            double wv = 0.0, mag = 0.0, cnd = 1.0;
             bool flagged = false, good = false;
             if (act) {
                 Stream st{key, g, s0 + j};
@@ -368,6 +375,8 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
                     double cond;
                     EB r = eval_point<EB>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond);
                     const double e = bound_of(r.a, cond);
+                    mag = r.a;
+                    cnd = cond;
                     wv = r.v * exp(-lp);
                     good = isfinite(wv);
                     flagged = good && !(e <= 1e-11 * fabs(r.v));
@@ -386,8 +395,11 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
                 FlagEntry& fe = w.flags[(uint64_t)t * w.tile + pos];
                 fe.sample = s0 + j;
                 fe.w = wv;
+                fe.mag = mag;
+                fe.cond = cnd;
                 fe.c1 = 0.0;
                 fe.c2 = 0.0;
+                fe.residual = 0;
             }
             nfl += __popcll(mask);
         }
@@ -432,6 +444,8 @@ __global__ void __launch_bounds__(64) k_fix_dd(const uint8_t* __restrict__ img, 
             LV<double> zv{zb + lane, 64};
             sample_point(D, W, G.M, st, zv, lp, order, tl);
             DD r = eval_point<DD>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond);
+            const double fdd = r.hi + r.lo;
+            fe.residual = !(bound_dd(fe.mag, fmax(cond, fe.cond), fdd) <= 1e-10 * fabs(fdd));
             const DD wd = r * exp(-lp);
             const DD d1 = wd - dd(fe.w);
             const DD d2 = wd * wd - two_prod(fe.w, fe.w);
@@ -451,7 +465,7 @@ __global__ void k_reduce(Work w, qa_acc* acc) {
     const uint64_t b = w.gtile0[g + 1] < t1 ? w.gtile0[g + 1] : t1;
     if (a >= b) return;
     DD s1{acc[g].s1_hi, acc[g].s1_lo}, s2{acc[g].s2_hi, acc[g].s2_lo};
-    uint64_t n = acc[g].n, nf = acc[g].n_flagged, nb = acc[g].n_bad;
+    uint64_t n = acc[g].n, nf = acc[g].n_flagged, nb = acc[g].n_bad, nr = acc[g].n_residual;
     for (uint64_t gt = a; gt < b; ++gt) {
         const uint32_t t = (uint32_t)(gt - t0);
         const Partial& p = w.partial[t];
@@ -463,12 +477,13 @@ __global__ void k_reduce(Work w, qa_acc* acc) {
             const FlagEntry& fe = w.flags[(uint64_t)t * w.tile + e];
             s1 = s1 + dd(fe.c1);
             s2 = s2 + dd(fe.c2);
+            nr += fe.residual;
         }
         nf += w.nflag[t];
     }
     acc[g].s1_hi = s1.hi; acc[g].s1_lo = s1.lo;
     acc[g].s2_hi = s2.hi; acc[g].s2_lo = s2.lo;
-    acc[g].n = n; acc[g].n_flagged = nf; acc[g].n_bad = nb;
+    acc[g].n = n; acc[g].n_flagged = nf; acc[g].n_bad = nb; acc[g].n_residual = nr;
 }
 
 // ---------------------------------------------------------------------------

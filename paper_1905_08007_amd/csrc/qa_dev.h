@@ -49,6 +49,8 @@ struct DevPiece {
 struct DevTable {
     int32_t nblocks;
     int32_t has_q;                         // Gamma_1 part present (A projector)
+    int32_t kstart[QA_MAXN + 1];           // blocks with k pairs: [kstart[k], kstart[k+1])
+    int32_t pad;
     double denom;                          // common denominator of the integer coefficients
     uint64_t hdr_off;                      // DevBlock[nblocks], sorted by k
     uint64_t coef_off;                     // double coefficients, blocks back to back
