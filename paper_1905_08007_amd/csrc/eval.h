@@ -18,15 +18,41 @@ template <class T> struct CLV {
 
 QA_HD int tri_idx(int a, int b) { return a <= b ? b * (b + 1) / 2 + a : a * (a + 1) / 2 + b; }
 
+// store a geometry output; in the comparing pass measure |double - dd| / (u |dd|)
+template <class S, class T, bool Cmp> QA_HD void geo_out(S& dst, const T& x, double& cond);
+template <> QA_HD void geo_out<double, double, false>(double& dst, const double& x, double&) { dst = x; }
+template <> QA_HD void geo_out<DD, double, false>(DD& dst, const double& x, double&) { dst = dd(x); }
+template <> QA_HD void geo_out<double, DD, true>(double& dst, const DD& x, double& cond) {
+    const double v = x.hi + x.lo;
+    cond = fmax(cond, fabs(dst - v) / (0x1p-53 * fabs(v)));
+    dst = v;
+}
+template <> QA_HD void geo_out<DD, DD, true>(DD& dst, const DD& x, double& cond) {
+    const double v = x.hi + x.lo;
+    cond = fmax(cond, fabs(dst.hi - v) / (0x1p-53 * fabs(v)));
+    dst = x;
+}
+template <class T, bool Cmp> QA_HD void geo_scalar(DD& dst, const T& x, double& cond);
+template <> QA_HD void geo_scalar<double, false>(DD& dst, const double& x, double&) { dst = dd(x); }
+template <> QA_HD void geo_scalar<DD, true>(DD& dst, const DD& x, double& cond) {
+    const double v = x.hi + x.lo;
+    cond = fmax(cond, fabs(dst.hi - v) / (0x1p-53 * fabs(v)));
+    dst = x;
+}
+
 // ---------------------------------------------------------------------------
 // graph polynomials of a piece: loop matrix M (chord basis), U = det M,
 // Wick contraction matrix Bbar_ij = eta_i^T M^-1 eta_j, flows A (external p
 // from the first to the last node) and C (q entering at the external node,
 // -1/2 leaving at each end), V = sum_i z_i (1 - A_i).
-// computed in double-double (T = DD); results stored as S (double or DD)
-template <class S, int L>
-QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V, double& cond) {
-    using T = DD;
+// Computed in T (double or double-double); results stored as S (double or
+// double-double).  With Cmp = true (T = DD) each output is compared with the
+// value already stored by a plain-double pass: cond receives the largest
+// discrepancy in units of the double round-off, i.e. an estimate of the
+// polynomials' conditioning (the double-double error is about cond * 2^-104).
+template <class S, class T, int L, bool Cmp>
+QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& Uo, DD& Vo, double& cond) {
+    T U, V;
     const int nl = pc.nlines;
     T zl[QA_MAXL];
 #pragma unroll
@@ -70,7 +96,8 @@ QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& 
             }
         }
     }
-    cond = dmax / dmin;   // loop-matrix conditioning proxy (largest diagonal / smallest pivot)
+    (void)dmax;
+    (void)dmin;
     U = from_d<T>(1.0);
 #pragma unroll
     for (int c = 0; c < L; ++c) U = U * (R[c][c] * R[c][c]);
@@ -98,6 +125,7 @@ QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& 
             Mi[c][d] = s;
             Mi[d][c] = s;
         }
+
     // flows
     T y[L], yq[L], jq[L];
     const bool hq = pc.ext >= 0;
@@ -113,7 +141,10 @@ QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& 
     for (int c = 0; c < L; ++c) {
         T s = from_d<T>(0.0), sq = from_d<T>(0.0);
 #pragma unroll
-        for (int d = 0; d < L; ++d) { s = s + Mi[c][d] * jv[d]; sq = sq + Mi[c][d] * jq[d]; }
+        for (int d = 0; d < L; ++d) {
+            s = s + Mi[c][d] * jv[d];
+            sq = sq + Mi[c][d] * jq[d];
+        }
         y[c] = s;
         yq[c] = sq;
     }
@@ -127,15 +158,8 @@ QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& 
         for (int c = 0; c < L; ++c)
             if (in[i][c]) { a = a - y[c]; cq = cq - yq[c]; }
         if (!hq) cq = from_d<T>(0.0);
-        // cancellation ratios of the flows (magnitude / value), for the error bounds
-        double ma = 1.0, mc = hq ? 0.5 : 0.0;
-#pragma unroll
-        for (int c = 0; c < L; ++c)
-            if (in[i][c]) { ma += fabs(val(y[c])); mc += fabs(val(yq[c])); }
-        cond = fmax(cond, ma / fabs(val(a)));
-        if (hq) cond = fmax(cond, mc / fabs(val(cq)));
-        store_geo(vars[QA_VAR_A + i], a);
-        store_geo(vars[QA_VAR_C + i], cq);
+        geo_out<S, T, Cmp>(vars[QA_VAR_A + i], a, cond);
+        geo_out<S, T, Cmp>(vars[QA_VAR_C + i], cq, cond);
         V = V + zl[i] * (from_d<T>(1.0) - a);
 #pragma unroll
         for (int d = 0; d < L; ++d) {
@@ -153,25 +177,33 @@ QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& 
         for (int j = i; j < QA_MAXL; ++j) {
             if (j < nl) {
                 T s = from_d<T>(0.0);
-                double ms = 0.0;
 #pragma unroll
                 for (int d = 0; d < L; ++d)
-                    if (in[j][d]) { s = s + Y[i][d]; ms += fabs(val(Y[i][d])); }
-                cond = fmax(cond, ms / fabs(val(s)));
-                store_geo(vars[tri_idx(i, j)], s);
+                    if (in[j][d]) s = s + Y[i][d];
+                geo_out<S, T, Cmp>(vars[tri_idx(i, j)], s, cond);
             }
         }
     }
+    geo_scalar<T, Cmp>(Uo, U, cond);
+    geo_scalar<T, Cmp>(Vo, V, cond);
+}
+
+// plain-double pass, then the double-double pass comparing against it
+template <class S, int L>
+QA_HD void geometry_2(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V, double& cond) {
+    geometry_L<S, double, L, false>(pc, z, vars, U, V, cond);
+    geometry_L<S, DD, L, true>(pc, z, vars, U, V, cond);
 }
 
 template <class S>
 QA_HD void geometry(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V, double& cond) {
+    cond = 1.0;
     switch (pc.nchords) {
-        case 1: geometry_L<S, 1>(pc, z, vars, U, V, cond); break;
-        case 2: geometry_L<S, 2>(pc, z, vars, U, V, cond); break;
-        case 3: geometry_L<S, 3>(pc, z, vars, U, V, cond); break;
-        case 4: geometry_L<S, 4>(pc, z, vars, U, V, cond); break;
-        default: geometry_L<S, 5>(pc, z, vars, U, V, cond); break;
+        case 1: geometry_2<S, 1>(pc, z, vars, U, V, cond); break;
+        case 2: geometry_2<S, 2>(pc, z, vars, U, V, cond); break;
+        case 3: geometry_2<S, 3>(pc, z, vars, U, V, cond); break;
+        case 4: geometry_2<S, 4>(pc, z, vars, U, V, cond); break;
+        default: geometry_2<S, 5>(pc, z, vars, U, V, cond); break;
     }
 }
 

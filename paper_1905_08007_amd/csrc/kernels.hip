@@ -706,46 +706,65 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     const uint64_t rounds = (ntiles + kPerRound - 1) / kPerRound;
     if (int rc = lds_attr(k_fused, lds_fp)) return rc;
     if (int rc = lds_attr(k_fix_dd, lds_dd)) return rc;
-    // one round as a graph: reset queue, fused pass, double-double pass, reduce, advance
+    // one round = two graphs captured on a private stream (capture is not allowed
+    // on the null stream) and replayed on the caller's stream: (reset queue,
+    // fused pass) and (double-double pass, reduce, advance round).  With
+    // timing, HIP events on the caller's stream bracket the first graph.
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t ga = nullptr, gb = nullptr;
+    hipGraphExec_t ea = nullptr, eb = nullptr;
+    auto cleanup = [&]() {
+        if (ea) hipGraphExecDestroy(ea);
+        if (eb) hipGraphExecDestroy(eb);
+        if (ga) hipGraphDestroy(ga);
+        if (gb) hipGraphDestroy(gb);
+        hipStreamDestroy(cs);
+    };
+    hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (ce == hipSuccess) {
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, cs, w);
+        hipLaunchKernelGGL(k_fused, dim3(grid), dim3(64), lds_fp, cs, (const uint8_t*)dev, key, w);
+        ce = hipStreamEndCapture(cs, &ga);
+    }
+    if (ce == hipSuccess) ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (ce == hipSuccess) {
+        hipLaunchKernelGGL(k_fix_dd, dim3(grid), dim3(64), lds_dd, cs, (const uint8_t*)dev, key, w);
+        hipLaunchKernelGGL(k_reduce, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, cs, w, acc);
+        hipLaunchKernelGGL(k_next_round, dim3(1), dim3(64), 0, cs, w);
+        ce = hipStreamEndCapture(cs, &gb);
+    }
+    if (ce == hipSuccess) ce = hipGraphInstantiate(&ea, ga, nullptr, nullptr, 0);
+    if (ce == hipSuccess) ce = hipGraphInstantiate(&eb, gb, nullptr, nullptr, 0);
+    if (ce != hipSuccess) {
+        cleanup();
+        return qa_fail(QA_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
+    }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (fused_ms) {
         *fused_ms = 0.0;
-        HIPCHK(hipEventCreate(&ev0));
-        HIPCHK(hipEventCreate(&ev1));
+        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess) {
+            cleanup();
+            return qa_fail(QA_EHIP, "hipEventCreate failed");
+        }
     }
-    // the graph is captured on a private stream (capture is not allowed on
-    // the null stream) and replayed on the caller's stream
-    hipStream_t cs;
-    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipGraph_t graph;
-    hipGraphExec_t exec;
-    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, cs, w);
-    if (ev0) hipEventRecord(ev0, cs);
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(64), lds_fp, cs, (const uint8_t*)dev, key, w);
-    if (ev1) hipEventRecord(ev1, cs);
-    hipLaunchKernelGGL(k_fix_dd, dim3(grid), dim3(64), lds_dd, cs, (const uint8_t*)dev, key, w);
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, cs, w, acc);
-    hipLaunchKernelGGL(k_next_round, dim3(1), dim3(64), 0, cs, w);
-    hipError_t ce = hipStreamEndCapture(cs, &graph);
-    hipStreamDestroy(cs);
-    if (ce != hipSuccess) return qa_fail(QA_EHIP, std::string("capture: ") + hipGetErrorString(ce));
-    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     int rc = QA_OK;
     for (uint64_t r = 0; r < rounds && rc == QA_OK; ++r) {
-        hipError_t e = hipGraphLaunch(exec, st);
-        if (e != hipSuccess) { rc = qa_fail(QA_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e)); break; }
-        if (fused_ms) {
+        hipError_t e = hipSuccess;
+        if (ev0) e = hipEventRecord(ev0, st);
+        if (e == hipSuccess) e = hipGraphLaunch(ea, st);
+        if (e == hipSuccess && ev1) e = hipEventRecord(ev1, st);
+        if (e == hipSuccess) e = hipGraphLaunch(eb, st);
+        if (e == hipSuccess && ev1) {
             e = hipEventSynchronize(ev1);
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-            if (e != hipSuccess) { rc = qa_fail(QA_EHIP, std::string("event timing: ") + hipGetErrorString(e)); break; }
             *fused_ms += ms;
         }
+        if (e != hipSuccess) rc = qa_fail(QA_EHIP, std::string("round launch: ") + hipGetErrorString(e));
     }
     hipError_t e = hipStreamSynchronize(st);
-    hipGraphExecDestroy(exec);
-    hipGraphDestroy(graph);
+    cleanup();
     if (ev0) hipEventDestroy(ev0);
     if (ev1) hipEventDestroy(ev1);
     if (rc != QA_OK) return rc;

@@ -86,6 +86,8 @@ def _eval_cmp(n, gis, npts, seed, gset=None):
             assert abs(fb[i] - v) <= eb[i] + 1e-12 * abs(v), (gi, i, fb[i], v, eb[i])
             assert abs(f0[i] - fb[i]) <= eb[i] + 1e-13 * abs(v), (gi, i)
             assert abs(fd[i] - v) <= ed[i] + 1e-15 * abs(v), (gi, i, fd[i], v, ed[i])
+            if residual:
+                assert i >= npts, ("an interior point needed more than double-double", gi, i)
             nres += int(residual)
     return nres
 
@@ -99,12 +101,12 @@ def test_eval_matches_oracle_2loop():
 
 
 def test_eval_matches_oracle_3loop():
-    # residual (beyond double-double) points appear only among the 1e-6 corner points
-    assert _eval_cmp(3, [0, 4, 8, 14, 19, 27], 24, 3) <= 6
+    # residual (beyond double-double) points may appear only among the 1e-6 corner points
+    _eval_cmp(3, [0, 4, 8, 14, 19, 27], 24, 3)
 
 
 def test_eval_matches_oracle_4loop():
-    assert _eval_cmp(4, [0, 100, 268], 4, 4) <= 3
+    _eval_cmp(4, [0, 100, 268], 4, 4)
 
 
 @pytest.mark.parametrize("n", [2, 3])
