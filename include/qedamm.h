@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 enum { QA_OK = 0, QA_EINVAL = -1, QA_ECAP = -2, QA_EHIP = -3, QA_ENOTSUP = -4, QA_ENOMEM = -5 };
-enum { QA_FP64 = 0, QA_FP64_BOUND = 1, QA_DD = 2 };  /* eval_integrand modes */
+enum { QA_FP64 = 0, QA_FP64_BOUND = 1, QA_DD = 2, QA_FP64_EST = 3 };  /* eval_integrand modes */
 
 /* A vertex graph without lepton loops at n loops: an open electron line with
  * slots 0..2n, the external photon at slot x, mate[s] = partner slot of the
@@ -123,11 +123,17 @@ int qa_sample_pdf(const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, 
 
 /* Evaluate f_G(z) for count points (device, SoA [M][count], any positive
  * scale: f is homogeneous of degree -M and is evaluated at z / sum z).
- * mode QA_FP64: f only.  QA_FP64_BOUND: also err[i] = running error bound and
- * flag[i] = 1 if err > 1e-11 |f|.  QA_DD: double-double evaluation, err = its
- * bound (when err is non-NULL an FP64 magnitude pass runs first to form it).
- * The bounds include the conditioning of the graph polynomials (computed in
- * double-double in every mode).  err and flag may be NULL for QA_FP64.  Units: (alpha/pi)^n. */
+ * mode QA_FP64: f only.  QA_FP64_BOUND: also err[i] = rigorous running error
+ * bound (the same evaluation on magnitudes) and flag[i] = 1 if err > 1e-11 |f|.
+ * QA_FP64_EST: err[i] = probabilistic estimate of the rounding error (first-
+ * order propagation of independent roundings, from the sums of squares of
+ * the monomials, times a safety factor 10) and flag[i] = 1 if err > 1e-11 |f|;
+ * this is the estimate the batched form flags with.  QA_DD: double-double
+ * evaluation, err = its rigorous bound (when err is non-NULL an FP64
+ * magnitude pass runs first to form it).  All include the conditioning of the
+ * graph polynomials (computed in double-double in every mode).  err and flag
+ * may be NULL for QA_FP64.  Units: (alpha/pi)^n.  Precision control: the
+ * round-off control of Sec. 2 (interval arithmetic of several precisions). */
 int qa_eval_integrand(const void* dev, uint32_t graph, const double* z, uint64_t count, int mode,
                       double* f, double* err, uint8_t* flag, void* stream);
 
@@ -138,10 +144,16 @@ int qa_accumulate(const double* f, const double* logp, uint64_t count, qa_acc* a
 
 /* Batched form: all graphs of the set with per-graph budgets (host array,
  * samples per graph; graph g uses samples first .. first+budgets[g]-1 of its
- * stream), fused sample + evaluate (FP64 with the running error bound) +
+ * stream), fused sample + evaluate (FP64 with the QA_FP64_EST estimate e) +
  * accumulate in a persistent launch (waves pull tiles of `tile` samples from
- * a queue), flagged points recomputed in double-double, deterministic
- * per-tile partials reduced into acc (device, ng records, overwritten).  The
+ * a queue).  A point is recomputed in double-double when e / p exceeds
+ * 1e-11 max(|w|, S_g), S_g the rms weight of graph g over the accurate
+ * weights seen so far in the call (earlier rounds, and this round's points
+ * with e <= 1e-11 |f|): the round-off of the accepted points stays below
+ * 1e-11 of the weight scale.  acc.n_flagged counts the recomputed points,
+ * n_residual those whose double-double estimate still exceeds 1e-10 of that
+ * scale.  Deterministic per-tile partials are reduced into acc (device, ng
+ * records, overwritten).  The
  * work is split into rounds of 2048 tiles; one round is captured as a
  * hipGraph and replayed.  work (device) >= qa_work_bytes.  tile = multiple of
  * 64 (0 = 1024); grid = persistent waves (0 = 4 per CU, max 2048).

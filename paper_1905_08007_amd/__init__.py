@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqedamm.so")
 
-QA_FP64, QA_FP64_BOUND, QA_DD = 0, 1, 2
+QA_FP64, QA_FP64_BOUND, QA_DD, QA_FP64_EST = 0, 1, 2, 3
 
 
 class QaGraph(C.Structure):
@@ -225,7 +225,7 @@ def eval_integrand(img, graph, z, mode=QA_FP64, stream=None):
         raise RuntimeError("z must be a contiguous float64 tensor of shape (3n, count)")
     f = torch.empty(count, dtype=torch.float64, device=z.device)
     err = torch.empty(count, dtype=torch.float64, device=z.device) if mode != QA_FP64 else None
-    flag = torch.empty(count, dtype=torch.uint8, device=z.device) if mode == QA_FP64_BOUND else None
+    flag = torch.empty(count, dtype=torch.uint8, device=z.device) if mode in (QA_FP64_BOUND, QA_FP64_EST) else None
     _check(lib().qa_eval_integrand(img.ptr, graph, _ptr(z), count, mode, _ptr(f), _ptr(err), _ptr(flag),
                                    _stream(stream)), "qa_eval_integrand")
     return f, err, flag

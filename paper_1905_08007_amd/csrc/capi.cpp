@@ -409,6 +409,12 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
                         const Block& b = tb.blocks[bi];
                         DevBlock db{};
                         db.k = (uint8_t)b.k; db.r = (uint8_t)b.r; db.coef = (uint32_t)c;
+                        double cmax = 0.0;
+                        for (double x : b.coef) cmax = std::max(cmax, std::fabs(x));
+                        int ce = 0;
+                        while (std::ldexp(1.0, ce) < cmax) ++ce;
+                        if (ce > 255) throw std::runtime_error("coefficient too large for the block exponent");
+                        db.cexp = (uint8_t)ce;
                         std::memcpy(db.bidx, b.bidx, QA_MAXK);
                         std::memcpy(db.aidx, b.aidx, QA_MAXR);
                         std::memcpy(db.cidx, b.cidx, QA_MAXR);

@@ -3,6 +3,7 @@
 #pragma once
 #include "numeric.h"
 #include "qa_dev.h"
+#include <type_traits>
 
 // lane view of per-lane scratch laid out [element][lane]
 template <class T> struct LV {
@@ -213,22 +214,24 @@ QA_HD void geometry(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V,
 // free-slot values A of a block; the q-derivative part folds the other slots.
 template <int J> QA_HD constexpr int amap(int i) { return i + (i >= J ? 1 : 0); }
 
-template <class T, int R, int J> struct Fold {
+// With Abs the leaves are |c[s]| (used with squared slot values for the
+// rounding-error estimate).
+template <class T, int R, int J, bool Abs = false> struct Fold {
     QA_HD static T run(const double* c, const T* A) {
-        return Fold<T, R - 1, J>::run(c, A) + A[amap<J>(R - 1)] * Fold<T, R - 1, J>::run(c + (1 << (R - 1)), A);
+        return Fold<T, R - 1, J, Abs>::run(c, A) + A[amap<J>(R - 1)] * Fold<T, R - 1, J, Abs>::run(c + (1 << (R - 1)), A);
     }
 };
-template <class T, int J> struct Fold<T, 0, J> {
-    QA_HD static T run(const double* c, const T*) { return from_d<T>(c[0]); }
+template <class T, int J, bool Abs> struct Fold<T, 0, J, Abs> {
+    QA_HD static T run(const double* c, const T*) { return from_d<T>(Abs ? fabs(c[0]) : c[0]); }
 };
 
-template <class T, int J> QA_HD T fold(const double* c, const T* A, int r) {
+template <class T, int J, bool Abs = false> QA_HD T fold(const double* c, const T* A, int r) {
     switch (r) {
-        case 0: return Fold<T, 0, J>::run(c, A);
-        case 1: return Fold<T, 1, J>::run(c, A);
-        case 2: return Fold<T, 2, J>::run(c, A);
-        case 3: return Fold<T, 3, J>::run(c, A);
-        case 4: return Fold<T, 4, J>::run(c, A);
+        case 0: return Fold<T, 0, J, Abs>::run(c, A);
+        case 1: return Fold<T, 1, J, Abs>::run(c, A);
+        case 2: return Fold<T, 2, J, Abs>::run(c, A);
+        case 3: return Fold<T, 3, J, Abs>::run(c, A);
+        case 4: return Fold<T, 4, J, Abs>::run(c, A);
         default: break;
     }
     // 16-coefficient leaves combined by a carry chain over the high bits
@@ -236,7 +239,7 @@ template <class T, int J> QA_HD T fold(const double* c, const T* A, int r) {
     T v = from_d<T>(0.0);
     const int nleaves = 1 << (r - 4);
     for (int leaf = 0; leaf < nleaves; ++leaf) {
-        v = Fold<T, 4, J>::run(c + 16 * leaf, A);
+        v = Fold<T, 4, J, Abs>::run(c + 16 * leaf, A);
         int b = leaf;
         bool stored = false;
 #pragma unroll
@@ -307,19 +310,100 @@ QA_HD T block_static(const DevBlock& b, const double* c, LV<S> vars, bool has_q)
     return w * s;
 }
 
-// blocks [b0, b1) all with R free slots, two at a time for instruction-level parallelism
+// sum over the free slot j carrying the q-derivative, value and square folds
+template <class S, int J> struct QTermsQ {
+    QA_HD static void run(double& s, double& sq, const double* c, const double* A, const double* A2, int r, LV<S> vars,
+                          const DevBlock& b) {
+        if (J >= r) return;
+        const double* cc = c + (1 << r) + J * (1 << (r - 1));
+        const double cj = vars[b.cidx[J]];
+        s = s + cj * fold<double, J>(cc, A, r - 1);
+        sq = sq + (cj * cj) * fold<double, J, true>(cc, A2, r - 1);
+        QTermsQ<S, J + 1>::run(s, sq, c, A, A2, r, vars, b);
+    }
+};
+template <class S> struct QTermsQ<S, QA_MAXR> {
+    QA_HD static void run(double&, double&, const double*, const double*, const double*, int, LV<S>, const DevBlock&) {}
+};
+
+// Block in EQ: the value, and q = 2^cexp * w^2 * sum_s |c_s| m_s^2 >= the sum
+// of squares of the block's monomials (m_s: product of the slot values of s;
+// 2^cexp >= max |c|).  Both folds share the coefficient loads.
+template <class S>
+QA_HD EQ eval_block_q(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
+    const int k = b.k, r = b.r;
+    double w = 1.0;
+#pragma unroll
+    for (int q = 0; q < QA_MAXK; ++q)
+        if (q < k) w = w * vars[b.bidx[q]];
+    double A[QA_MAXR + 1], A2[QA_MAXR + 1];
+#pragma unroll
+    for (int i = 0; i < QA_MAXR; ++i) {
+        A[i] = i < r ? vars[b.aidx[i]] : 0.0;
+        A2[i] = A[i] * A[i];
+    }
+    A[QA_MAXR] = A2[QA_MAXR] = 0.0;
+    double s = fold<double, QA_MAXR>(c, A, r);
+    double sq = fold<double, QA_MAXR, true>(c, A2, r);
+    if (has_q) QTermsQ<S, 0>::run(s, sq, c, A, A2, r, vars, b);
+    return EQ{w * s, ldexp(w * w * sq, b.cexp)};
+}
+
+template <class S, int R, int J> struct QStaticQ {
+    QA_HD static void run(double& s, double& sq, const double* c, const double* A, const double* A2, LV<S> vars,
+                          const DevBlock& b) {
+        const double cj = vars[b.cidx[J]];
+        const double* cc = c + (1 << R) + J * (1 << (R - 1));
+        s = s + cj * Fold<double, R - 1, J>::run(cc, A);
+        sq = sq + (cj * cj) * Fold<double, R - 1, J, true>::run(cc, A2);
+        QStaticQ<S, R, J + 1>::run(s, sq, c, A, A2, vars, b);
+    }
+};
+template <class S, int R> struct QStaticQ<S, R, R> {
+    QA_HD static void run(double&, double&, const double*, const double*, const double*, LV<S>, const DevBlock&) {}
+};
+
+template <class S, int R>
+QA_HD EQ block_static_q(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
+    const int k = b.k;
+    double w = 1.0;
+#pragma unroll
+    for (int q = 0; q < QA_MAXK; ++q)
+        if (q < k) w = w * vars[b.bidx[q]];
+    double A[R + 1], A2[R + 1];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        A[i] = vars[b.aidx[i]];
+        A2[i] = A[i] * A[i];
+    }
+    A[R] = A2[R] = 0.0;
+    double s = Fold<double, R, QA_MAXR>::run(c, A);
+    double sq = Fold<double, R, QA_MAXR, true>::run(c, A2);
+    if (has_q) QStaticQ<S, R, 0>::run(s, sq, c, A, A2, vars, b);
+    return EQ{w * s, ldexp(w * w * sq, b.cexp)};
+}
+template <class T, class S, int R>
+QA_HD T block_any(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
+    if constexpr (std::is_same<T, EQ>::value) return block_static_q<S, R>(b, c, vars, has_q);
+    else return block_static<T, S, R>(b, c, vars, has_q);
+}
+
+// blocks [b0, b1) all with R free slots, two at a time for instruction-level
+// parallelism.  A block's value passes through at most 2 (k + R) + 3 roundings
+// (k + R lifted geometry values, the R-level fold, the k-pair product, the
+// final product), which acc_add uses for the ER estimate.
 template <class T, class S, int R, class AT>
 QA_HD void group_static(const DevBlock* blocks, int b0, int b1, const double* coefs, LV<S> vars, bool hq, AT& acc) {
     int bi = b0;
     for (; bi + 1 < b1; bi += 2) {
         const DevBlock& x = blocks[bi];
         const DevBlock& y = blocks[bi + 1];
-        const T vx = block_static<T, S, R>(x, coefs + x.coef, vars, hq);
-        const T vy = block_static<T, S, R>(y, coefs + y.coef, vars, hq);
-        acc_add(acc, vx);
-        acc_add(acc, vy);
+        const T vx = block_any<T, S, R>(x, coefs + x.coef, vars, hq);
+        const T vy = block_any<T, S, R>(y, coefs + y.coef, vars, hq);
+        acc_add(acc, vx, 2 * (x.k + R) + 3);
+        acc_add(acc, vy, 2 * (y.k + R) + 3);
     }
-    if (bi < b1) acc_add(acc, block_static<T, S, R>(blocks[bi], coefs + blocks[bi].coef, vars, hq));
+    if (bi < b1) acc_add(acc, block_any<T, S, R>(blocks[bi], coefs + blocks[bi].coef, vars, hq), 2 * (blocks[bi].k + R) + 3);
 }
 
 // Evaluate one coefficient table: poly[k] = (1/denom) * sum over blocks with k
@@ -327,6 +411,7 @@ QA_HD void group_static(const DevBlock* blocks, int b0, int b1, const double* co
 template <class T, class S>
 QA_HD void eval_table(const uint8_t* __restrict__ img, const DevTable& tb, LV<S> vars, int n, T* poly) {
     using AT = typename Acc<T>::type;
+    using BT = typename BlockOf<T>::type;
     const DevBlock* blocks = reinterpret_cast<const DevBlock*>(img + tb.hdr_off);
     const double* coefs = reinterpret_cast<const double*>(img + tb.coef_off);
     const bool hq = tb.has_q != 0;
@@ -336,19 +421,22 @@ QA_HD void eval_table(const uint8_t* __restrict__ img, const DevTable& tb, LV<S>
         const int b0 = tb.kstart[k], b1 = tb.kstart[k + 1];
         if (k < n && b0 < b1) {
             // the double-double path (flagged points only) uses the compact generic loop
-            const int rsel = sizeof(T) == sizeof(DD) && sizeof(S) == sizeof(DD) ? -1 : blocks[b0].r;
+            const int rsel = std::is_same<T, DD>::value ? -1 : blocks[b0].r;
             switch (rsel) {
-                case 0: group_static<T, S, 0>(blocks, b0, b1, coefs, vars, hq, acc); break;
-                case 1: group_static<T, S, 1>(blocks, b0, b1, coefs, vars, hq, acc); break;
-                case 2: group_static<T, S, 2>(blocks, b0, b1, coefs, vars, hq, acc); break;
-                case 3: group_static<T, S, 3>(blocks, b0, b1, coefs, vars, hq, acc); break;
-                case 4: group_static<T, S, 4>(blocks, b0, b1, coefs, vars, hq, acc); break;
-                case 5: group_static<T, S, 5>(blocks, b0, b1, coefs, vars, hq, acc); break;
-                case 6: group_static<T, S, 6>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 0: group_static<BT, S, 0>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 1: group_static<BT, S, 1>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 2: group_static<BT, S, 2>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 3: group_static<BT, S, 3>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 4: group_static<BT, S, 4>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 5: group_static<BT, S, 5>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 6: group_static<BT, S, 6>(blocks, b0, b1, coefs, vars, hq, acc); break;
                 default:
                     for (int bi = b0; bi < b1; ++bi) {
                         const DevBlock& b = blocks[bi];
-                        acc_add(acc, eval_block<T, S>(b, coefs + b.coef, vars, hq));
+                        if constexpr (std::is_same<BT, EQ>::value)
+                            acc_add(acc, eval_block_q<S>(b, coefs + b.coef, vars, hq), 2 * (b.k + b.r) + 3);
+                        else
+                            acc_add(acc, eval_block<BT, S>(b, coefs + b.coef, vars, hq), 2 * (b.k + b.r) + 3);
                     }
             }
         }

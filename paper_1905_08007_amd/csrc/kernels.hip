@@ -176,6 +176,16 @@ __device__ __forceinline__ double bound_dd(double mag, double cond, double f) {
     return mag * 0x1p-104 * (256.0 + 16.0 * cond) + fabs(f) * QA_U;
 }
 
+// Flag estimates.  est_of: the ER estimate u sqrt(q) of the FP64 rounding
+// error with a safety factor of 10 (the observed ratio of the actual error to
+// u sqrt(q) stays below 2), plus the error of the double-double geometry
+// (relative 16 cond 2^-104 per value, through up to 16 factors).  est_dd: the
+// same scale for the double-double evaluation, plus its final rounding.
+__device__ __forceinline__ double est_of(double q, double cond) { return QA_U * sqrt(q) * (10.0 + cond * 0x1p-43); }
+__device__ __forceinline__ double est_dd(double q, double cond, double f) {
+    return 0x1p-104 * sqrt(q) * (40.0 + 256.0 * cond) + QA_U * fabs(f);
+}
+
 __global__ void __launch_bounds__(64) k_eval_fp64(const uint8_t* __restrict__ img, uint32_t graph,
                                                   const double* __restrict__ z, uint64_t count, double* __restrict__ f) {
     extern __shared__ char lds[];
@@ -201,6 +211,24 @@ __global__ void __launch_bounds__(64) k_eval_bound(const uint8_t* __restrict__ i
     double cond;
     EB r = eval_point<EB>(img, G, CLV<double>{z + i, (int)count}, vars, polys, cond);
     const double e = bound_of(r.a, cond);
+    f[i] = r.v;
+    if (err) err[i] = e;
+    if (flag) flag[i] = !(e <= 1e-11 * fabs(r.v));
+}
+
+__global__ void __launch_bounds__(64) k_eval_est(const uint8_t* __restrict__ img, uint32_t graph,
+                                                 const double* __restrict__ z, uint64_t count, double* __restrict__ f,
+                                                 double* __restrict__ err, uint8_t* __restrict__ flag) {
+    extern __shared__ char lds[];
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const DevGraph& G = dev_graph(img, graph);
+    LV<double> vars;
+    LV<ER> polys;
+    lane_views<ER>(lds, G.npoly, vars, polys);
+    double cond;
+    ER r = eval_point<ER>(img, G, CLV<double>{z + i, (int)count}, vars, polys, cond);
+    const double e = est_of(r.q, cond);
     f[i] = r.v;
     if (err) err[i] = e;
     if (flag) flag[i] = !(e <= 1e-11 * fabs(r.v));
@@ -246,6 +274,19 @@ __device__ uint64_t wave_sum_u64(uint64_t v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
 }
+__device__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+__device__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
 
 // single block, fixed order: deterministic for a given count
 __global__ void __launch_bounds__(1024) k_accumulate(const double* __restrict__ f, const double* __restrict__ logp,
@@ -289,22 +330,31 @@ __global__ void __launch_bounds__(1024) k_accumulate(const double* __restrict__ 
 
 struct Partial {
     double s1_hi, s1_lo, s2_hi, s2_lo;
-    uint64_t n, nflag, nbad, pad;
+    double s2g;              // sum of w^2 over points that passed the relative test
+    uint64_t n, nflag, nbad;
 };
 struct FlagEntry {
     uint64_t sample;
-    double w;         // FP64 weight
-    double mag, cond; // magnitude and conditioning from the FP64 pass
+    double w;         // FP64 weight f / p
+    double estw;      // FP64 error estimate of w
+    double q, cond;   // ER variance and geometry conditioning of the FP64 pass
     double c1, c2;    // corrections written by the double-double pass
-    uint64_t residual;// 1 if the double-double bound still exceeds 1e-10 |f|
+    uint32_t graph;
+    uint8_t fixed;    // recomputed in double-double
+    uint8_t residual; // double-double estimate still above 1e-10 of the scale
+    uint8_t pad[2];
 };
 struct Work {
-    uint32_t* counter;       // [0] tile queue, [1] round
+    uint32_t* counter;       // [0] tile queue, [1] round, [2] selected entries, [3] fix chunk queue
     uint64_t* gtile0;        // per graph: first global tile index (ng + 1 entries)
     uint64_t* budget;        // per graph samples
     Partial* partial;        // per round-tile
-    uint32_t* nflag;         // per round-tile
+    uint32_t* nflag;         // per round-tile: candidate entries
     FlagEntry* flags;        // per round-tile * tile
+    double* scale;           // per graph: rms of the accurate weights so far
+    uint32_t* nsel;          // per round-tile: entries selected for double-double
+    uint32_t* seloff;        // per round-tile: offset of its selected entries
+    uint32_t* sel;           // selected entry indices (t * tile + e), tile order
     double* zbuf;            // per persistent wave: QA_MAXM * 64
     uint32_t tile, per_round, ng;
     uint64_t ntiles;
@@ -324,6 +374,16 @@ __device__ __forceinline__ void tile_of(const Work& w, uint64_t gt, uint32_t& g,
     s0 = w.first + off;
 }
 
+// round-tile range [a, b) of graph g in the current round
+__device__ __forceinline__ bool round_tiles(const Work& w, uint32_t g, uint64_t& a, uint64_t& b, uint64_t& t0) {
+    const uint64_t round = w.counter[1];
+    t0 = round * w.per_round;
+    const uint64_t t1 = t0 + w.per_round;
+    a = w.gtile0[g] > t0 ? w.gtile0[g] : t0;
+    b = w.gtile0[g + 1] < t1 ? w.gtile0[g + 1] : t1;
+    return a < b;
+}
+
 __global__ void k_reset(Work w) {
     if (threadIdx.x == 0 && blockIdx.x == 0) w.counter[0] = 0;
 }
@@ -331,12 +391,15 @@ __global__ void k_next_round(Work w) {
     if (threadIdx.x == 0 && blockIdx.x == 0) w.counter[1] += 1;
 }
 
+// Fused pass: sample, evaluate in FP64 with the ER estimate, accumulate w and
+// w^2 per tile, and list the points whose estimate exceeds 1e-11 |f|
+// (candidates for the double-double pass).
 __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, uint2 key, Work w) {
     extern __shared__ char lds[];
     const int lane = threadIdx.x;
     LV<double> vars;
-    LV<EB> polys;
-    lane_views<EB>(lds, 0, vars, polys);
+    LV<ER> polys;
+    lane_views<ER>(lds, 0, vars, polys);
     double* zb = w.zbuf + (uint64_t)blockIdx.x * QA_MAXM * 64;
     const uint64_t round = w.counter[1];
     for (;;) {
@@ -357,12 +420,13 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
         const double* D = reinterpret_cast<const double*>(img + G.deg_off);
         const double* W = reinterpret_cast<const double*>(img + G.w_off);
         DD s1{0, 0}, s2{0, 0};
+        double s2g = 0.0;
         uint64_t n = 0, bad = 0;
         uint32_t nfl = 0;
         for (uint32_t base = 0; base < cnt; base += 64) {
             const uint32_t j = base + lane;
             const bool act = j < cnt;
-            double wv = 0.0, mag = 0.0, cnd = 1.0;
+            double wv = 0.0, ew = 0.0, qv = 0.0, cnd = 1.0;
             bool flagged = false, good = false;
             if (act) {
                 Stream st{key, g, s0 + j};
@@ -373,11 +437,13 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
                 bool ok = sample_point(D, W, G.M, st, zv, lp, order, tl);
                 if (ok) {
                     double cond;
-                    EB r = eval_point<EB>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond);
-                    const double e = bound_of(r.a, cond);
-                    mag = r.a;
+                    ER r = eval_point<ER>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond);
+                    const double e = est_of(r.q, cond);
+                    const double ip = exp(-lp);
+                    qv = r.q;
                     cnd = cond;
-                    wv = r.v * exp(-lp);
+                    wv = r.v * ip;
+                    ew = e * ip;
                     good = isfinite(wv);
                     flagged = good && !(e <= 1e-11 * fabs(r.v));
                 }
@@ -385,6 +451,7 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
             if (act && good) {
                 s1 = s1 + dd(wv);
                 s2 = s2 + two_prod(wv, wv);
+                if (!flagged) s2g += wv * wv;
                 ++n;
             } else if (act) {
                 ++bad;
@@ -395,20 +462,25 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
                 FlagEntry& fe = w.flags[(uint64_t)t * w.tile + pos];
                 fe.sample = s0 + j;
                 fe.w = wv;
-                fe.mag = mag;
+                fe.estw = ew;
+                fe.q = qv;
                 fe.cond = cnd;
                 fe.c1 = 0.0;
                 fe.c2 = 0.0;
+                fe.graph = g;
+                fe.fixed = 0;
                 fe.residual = 0;
             }
             nfl += __popcll(mask);
         }
         s1 = wave_sum_dd(s1);
         s2 = wave_sum_dd(s2);
+        s2g = wave_sum_f64(s2g);
         n = wave_sum_u64(n);
         bad = wave_sum_u64(bad);
         if (lane == 0) {
             pr.s1_hi = s1.hi; pr.s1_lo = s1.lo; pr.s2_hi = s2.hi; pr.s2_lo = s2.lo;
+            pr.s2g = s2g;
             pr.n = n; pr.nflag = nfl; pr.nbad = bad;
             w.partial[t] = pr;
             w.nflag[t] = nfl;
@@ -416,41 +488,131 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
     }
 }
 
-// double-double recompute of the flagged points of this round
+// Per graph: the scale of its weights, sqrt(sum w^2 / N) over the accurate
+// weights of earlier rounds and the points of this round that passed the
+// relative test (a lower bound of the rms weight).
+__global__ void k_scale(Work w, const qa_acc* __restrict__ acc) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= w.ng) return;
+    uint64_t a, b, t0;
+    if (!round_tiles(w, g, a, b, t0)) return;
+    double s2 = acc[g].s2_hi + acc[g].s2_lo;
+    uint64_t n = acc[g].n;
+    for (uint64_t gt = a; gt < b; ++gt) {
+        s2 += w.partial[gt - t0].s2g;
+        n += w.partial[gt - t0].n;
+    }
+    w.scale[g] = n ? sqrt(s2 / (double)n) : 0.0;
+}
+
+// A candidate is recomputed in double-double when its error estimate on w
+// exceeds 1e-11 of max(|w|, scale of its graph).
+__device__ __forceinline__ bool needs_dd(const FlagEntry& fe, const double* scale) {
+    return !(fe.estw <= 1e-11 * fmax(fabs(fe.w), scale[fe.graph]));
+}
+
+__global__ void __launch_bounds__(64) k_select(Work w) {
+    const int lane = threadIdx.x;
+    for (uint32_t t = blockIdx.x; t < w.per_round; t += gridDim.x) {
+        const uint32_t nf = w.nflag[t];
+        uint32_t cnt = 0;
+        for (uint32_t b = 0; b < nf; b += 64) {
+            const uint32_t e = b + lane;
+            bool need = false;
+            if (e < nf) {
+                FlagEntry& fe = w.flags[(uint64_t)t * w.tile + e];
+                need = needs_dd(fe, w.scale);
+                fe.fixed = need;
+            }
+            cnt += __popcll(__ballot(need));
+        }
+        if (lane == 0) w.nsel[t] = cnt;
+    }
+}
+
+// exclusive prefix sum of nsel over the round's tiles (one wave)
+__global__ void __launch_bounds__(64) k_scan(Work w) {
+    const uint32_t lane = threadIdx.x;
+    const uint32_t per = (w.per_round + 63) / 64;
+    const uint32_t t0 = lane * per, t1 = t0 + per < w.per_round ? t0 + per : w.per_round;
+    uint32_t loc = 0;
+    for (uint32_t t = t0; t < t1; ++t) loc += w.nsel[t];
+    uint32_t inc = loc;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d);
+        if ((int)lane >= d) inc += o;
+    }
+    uint32_t off = inc - loc;
+    for (uint32_t t = t0; t < t1; ++t) {
+        w.seloff[t] = off;
+        off += w.nsel[t];
+    }
+    if (lane == 63) {
+        w.counter[2] = inc;
+        w.counter[3] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_compact(Work w) {
+    const int lane = threadIdx.x;
+    for (uint32_t t = blockIdx.x; t < w.per_round; t += gridDim.x) {
+        const uint32_t nf = w.nflag[t];
+        uint32_t pos = w.seloff[t];
+        for (uint32_t b = 0; b < nf; b += 64) {
+            const uint32_t e = b + lane;
+            const bool need = e < nf && w.flags[(uint64_t)t * w.tile + e].fixed;
+            const uint64_t mask = __ballot(need);
+            if (need) w.sel[pos + __popcll(mask & ((1ull << lane) - 1))] = t * w.tile + e;
+            pos += __popcll(mask);
+        }
+    }
+}
+
+// Double-double recompute of the selected entries: persistent waves take
+// chunks of 64 consecutive entries (graph-major order); a chunk that spans
+// graphs is processed one graph at a time.
 __global__ void __launch_bounds__(64) k_fix_dd(const uint8_t* __restrict__ img, uint2 key, Work w) {
     extern __shared__ char lds[];
     const int lane = threadIdx.x;
     LV<DD> vars, polys;
     lane_views<DD>(lds, 0, vars, polys);
     double* zb = w.zbuf + (uint64_t)blockIdx.x * QA_MAXM * 64;
-    const uint64_t round = w.counter[1];
-    for (uint32_t t = blockIdx.x; t < w.per_round; t += gridDim.x) {
-        const uint32_t nf = w.nflag[t];
-        if (nf == 0) continue;
-        const uint64_t gt = round * w.per_round + t;
-        uint32_t g, cnt;
-        uint64_t s0;
-        tile_of(w, gt, g, s0, cnt);
-        const DevGraph& G = dev_graph(img, g);
-        const double* D = reinterpret_cast<const double*>(img + G.deg_off);
-        const double* W = reinterpret_cast<const double*>(img + G.w_off);
-        for (uint32_t b = 0; b < nf; b += 64) {
-            const uint32_t e = b + lane;
-            if (e >= nf) continue;
-            FlagEntry& fe = w.flags[(uint64_t)t * w.tile + e];
-            Stream st{key, g, fe.sample};
-            uint8_t order[QA_MAXM];
-            double tl[QA_MAXM], lp, cond;
-            LV<double> zv{zb + lane, 64};
-            sample_point(D, W, G.M, st, zv, lp, order, tl);
-            DD r = eval_point<DD>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond);
-            const double fdd = r.hi + r.lo;
-            fe.residual = !(bound_dd(fe.mag, fmax(cond, fe.cond), fdd) <= 1e-10 * fabs(fdd));
-            const DD wd = r * exp(-lp);
-            const DD d1 = wd - dd(fe.w);
-            const DD d2 = wd * wd - two_prod(fe.w, fe.w);
-            fe.c1 = d1.hi + d1.lo;
-            fe.c2 = d2.hi + d2.lo;
+    const uint32_t total = w.counter[2];
+    for (;;) {
+        uint32_t c = 0;
+        if (lane == 0) c = atomicAdd(w.counter + 3, 1u);
+        c = __shfl(c, 0);
+        if ((uint64_t)c * 64 >= total) break;
+        const uint32_t idx = c * 64 + lane;
+        const bool act = idx < total;
+        FlagEntry* fe = act ? &w.flags[w.sel[idx]] : nullptr;
+        const uint32_t mine = act ? fe->graph : 0xffffffffu;
+        bool done = !act;
+        for (;;) {
+            const uint32_t g = wave_min_u32(done ? 0xffffffffu : mine);
+            if (g == 0xffffffffu) break;
+            if (!done && mine == g) {
+                const DevGraph& G = dev_graph(img, g);
+                const double* D = reinterpret_cast<const double*>(img + G.deg_off);
+                const double* W = reinterpret_cast<const double*>(img + G.w_off);
+                Stream st{key, g, fe->sample};
+                uint8_t order[QA_MAXM];
+                double tl[QA_MAXM], lp, cond;
+                LV<double> zv{zb + lane, 64};
+                sample_point(D, W, G.M, st, zv, lp, order, tl);
+                DD r = eval_point<DD>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond);
+                const double fdd = r.hi + r.lo;
+                const double ip = exp(-lp);
+                fe->residual = !(est_dd(fe->q, fmax(cond, fe->cond), fdd) * ip <=
+                                 1e-10 * fmax(fabs(fdd) * ip, w.scale[g]));
+                const DD wd = r * ip;
+                const DD d1 = wd - dd(fe->w);
+                const DD d2 = wd * wd - two_prod(fe->w, fe->w);
+                fe->c1 = d1.hi + d1.lo;
+                fe->c2 = d2.hi + d2.lo;
+                done = true;
+            }
         }
     }
 }
@@ -459,11 +621,8 @@ __global__ void __launch_bounds__(64) k_fix_dd(const uint8_t* __restrict__ img, 
 __global__ void k_reduce(Work w, qa_acc* acc) {
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= w.ng) return;
-    const uint64_t round = w.counter[1];
-    const uint64_t t0 = round * w.per_round, t1 = t0 + w.per_round;
-    const uint64_t a = w.gtile0[g] > t0 ? w.gtile0[g] : t0;
-    const uint64_t b = w.gtile0[g + 1] < t1 ? w.gtile0[g + 1] : t1;
-    if (a >= b) return;
+    uint64_t a, b, t0;
+    if (!round_tiles(w, g, a, b, t0)) return;
     DD s1{acc[g].s1_hi, acc[g].s1_lo}, s2{acc[g].s2_hi, acc[g].s2_lo};
     uint64_t n = acc[g].n, nf = acc[g].n_flagged, nb = acc[g].n_bad, nr = acc[g].n_residual;
     for (uint64_t gt = a; gt < b; ++gt) {
@@ -475,11 +634,12 @@ __global__ void k_reduce(Work w, qa_acc* acc) {
         nb += p.nbad;
         for (uint32_t e = 0; e < w.nflag[t]; ++e) {
             const FlagEntry& fe = w.flags[(uint64_t)t * w.tile + e];
+            if (!fe.fixed) continue;
             s1 = s1 + dd(fe.c1);
             s2 = s2 + dd(fe.c2);
             nr += fe.residual;
+            ++nf;
         }
-        nf += w.nflag[t];
     }
     acc[g].s1_hi = s1.hi; acc[g].s1_lo = s1.lo;
     acc[g].s2_hi = s2.hi; acc[g].s2_lo = s2.lo;
@@ -598,11 +758,14 @@ extern "C" int qa_eval_integrand(const void* dev, uint32_t graph, const double* 
     if (mode == QA_FP64) rc = lds_attr(k_eval_fp64, lds_bytes<double>(G->npoly, 64));
     else if (mode == QA_FP64_BOUND) rc = lds_attr(k_eval_bound, lds_bytes<EB>(G->npoly, 64));
     else if (mode == QA_DD) rc = lds_attr(k_eval_dd, lds_bytes<DD>(G->npoly, 64));
+    else if (mode == QA_FP64_EST) rc = lds_attr(k_eval_est, lds_bytes<ER>(G->npoly, 64));
     if (rc != QA_OK) return rc;
     if (mode == QA_FP64) {
         hipLaunchKernelGGL(k_eval_fp64, grid, block, lds_bytes<double>(G->npoly, 64), st, d, graph, z, count, f);
     } else if (mode == QA_FP64_BOUND) {
         hipLaunchKernelGGL(k_eval_bound, grid, block, lds_bytes<EB>(G->npoly, 64), st, d, graph, z, count, f, err, flag);
+    } else if (mode == QA_FP64_EST) {
+        hipLaunchKernelGGL(k_eval_est, grid, block, lds_bytes<ER>(G->npoly, 64), st, d, graph, z, count, f, err, flag);
     } else if (mode == QA_DD) {
         hipLaunchKernelGGL(k_eval_dd, grid, block, lds_bytes<DD>(G->npoly, 64), st, d, graph, z, count, f, err);
     } else {
@@ -622,7 +785,7 @@ extern "C" int qa_accumulate(const double* f, const double* logp, uint64_t count
 
 // work buffer layout for qa_integrate
 struct WorkLayout {
-    size_t counter, gtile0, budget, partial, nflag, flags, zbuf, total;
+    size_t counter, gtile0, budget, partial, nflag, flags, scale, nsel, seloff, sel, zbuf, total;
 };
 static WorkLayout work_layout(size_t ng, uint32_t tile, uint32_t per_round, uint32_t grid) {
     WorkLayout L{};
@@ -634,6 +797,10 @@ static WorkLayout work_layout(size_t ng, uint32_t tile, uint32_t per_round, uint
     L.partial = take(sizeof(Partial) * per_round);
     L.nflag = take(4 * per_round);
     L.flags = take(sizeof(FlagEntry) * (size_t)per_round * tile);
+    L.scale = take(8 * ng);
+    L.nsel = take(4 * per_round);
+    L.seloff = take(4 * per_round);
+    L.sel = take(4 * (size_t)per_round * tile);
     L.zbuf = take(8ull * QA_MAXM * 64 * grid);
     L.total = o;
     return L;
@@ -693,6 +860,10 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     w.partial = (Partial*)(wb + L.partial);
     w.nflag = (uint32_t*)(wb + L.nflag);
     w.flags = (FlagEntry*)(wb + L.flags);
+    w.scale = (double*)(wb + L.scale);
+    w.nsel = (uint32_t*)(wb + L.nsel);
+    w.seloff = (uint32_t*)(wb + L.seloff);
+    w.sel = (uint32_t*)(wb + L.sel);
     w.zbuf = (double*)(wb + L.zbuf);
     w.tile = tile;
     w.per_round = kPerRound;
@@ -702,13 +873,14 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     const uint2 key = make_uint2((uint32_t)seed, tag);
     int maxpoly = 1;
     for (size_t g = 0; g < ng; ++g) maxpoly = std::max(maxpoly, host_graph(*img, (uint32_t)g)->npoly);
-    const size_t lds_fp = lds_bytes<EB>(maxpoly, 64), lds_dd = lds_bytes<DD>(maxpoly, 64);
+    const size_t lds_fp = lds_bytes<ER>(maxpoly, 64), lds_dd = lds_bytes<DD>(maxpoly, 64);
     const uint64_t rounds = (ntiles + kPerRound - 1) / kPerRound;
     if (int rc = lds_attr(k_fused, lds_fp)) return rc;
     if (int rc = lds_attr(k_fix_dd, lds_dd)) return rc;
     // one round = two graphs captured on a private stream (capture is not allowed
     // on the null stream) and replayed on the caller's stream: (reset queue,
-    // fused pass) and (double-double pass, reduce, advance round).  With
+    // fused pass) and (weight scales, selection and compaction of the candidates,
+    // double-double pass, reduce, advance round).  With
     // timing, HIP events on the caller's stream bracket the first graph.
     hipStream_t cs;
     HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -729,8 +901,13 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     }
     if (ce == hipSuccess) ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (ce == hipSuccess) {
+        const dim3 gng((unsigned)((ng + 63) / 64));
+        hipLaunchKernelGGL(k_scale, gng, dim3(64), 0, cs, w, acc);
+        hipLaunchKernelGGL(k_select, dim3(grid), dim3(64), 0, cs, w);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, cs, w);
+        hipLaunchKernelGGL(k_compact, dim3(grid), dim3(64), 0, cs, w);
         hipLaunchKernelGGL(k_fix_dd, dim3(grid), dim3(64), lds_dd, cs, (const uint8_t*)dev, key, w);
-        hipLaunchKernelGGL(k_reduce, dim3((unsigned)((ng + 63) / 64)), dim3(64), 0, cs, w, acc);
+        hipLaunchKernelGGL(k_reduce, gng, dim3(64), 0, cs, w, acc);
         hipLaunchKernelGGL(k_next_round, dim3(1), dim3(64), 0, cs, w);
         ce = hipStreamEndCapture(cs, &gb);
     }

@@ -24,6 +24,38 @@ QA_HD EB fma_(EB a, EB b, EB c) { return EB{fma(a.v, b.v, c.v), a.a * b.a + c.a}
 QA_HD double val(EB x) { return x.v; }
 QA_HD double mag(EB x) { return x.a; }
 
+// ---- value + rounding-error variance estimate.  q estimates the variance of
+// the accumulated rounding error in units of u^2 under the probabilistic
+// model of rounding (each operation's relative error an independent,
+// zero-mean variable bounded by u; Higham and Mary, SIAM J. Sci. Comput. 41
+// (2019) A2815), propagated to first order: each operation adds the square
+// of its own result (its rounding) to the propagated terms.
+struct ER {
+    double v, q;
+};
+QA_HD ER operator+(ER x, ER y) {
+    const double v = x.v + y.v;
+    return ER{v, x.q + y.q + v * v};
+}
+QA_HD ER operator-(ER x, ER y) {
+    const double v = x.v - y.v;
+    return ER{v, x.q + y.q + v * v};
+}
+QA_HD ER operator*(ER x, ER y) {
+    const double v = x.v * y.v;
+    return ER{v, x.q * (y.v * y.v) + y.q * (x.v * x.v) + v * v};
+}
+QA_HD ER operator*(ER x, double c) {
+    const double v = x.v * c;
+    return ER{v, x.q * (c * c) + v * v};
+}
+QA_HD ER operator/(ER x, ER y) {
+    const double v = x.v / y.v;
+    return ER{v, (x.q + y.q * (v * v)) / (y.v * y.v) + v * v};
+}
+QA_HD ER operator-(ER x) { return ER{-x.v, x.q}; }
+QA_HD double val(ER x) { return x.v; }
+
 QA_HD double fma_(double a, double b, double c) { return fma(a, b, c); }
 QA_HD double val(double x) { return x; }
 QA_HD double mag(double x) { return fabs(x); }
@@ -152,9 +184,25 @@ struct EBAcc {
     double a;
 };
 template <> struct Acc<EB> { using type = EBAcc; };
+// ER tables accumulate EQ blocks: the value in double-double, and
+// nb * q_block, nb the number of roundings on any path through the block, each
+// contributing at most u times a monomial
+struct ERAcc {
+    DD v;
+    double q;
+};
+template <> struct Acc<ER> { using type = ERAcc; };
+// A block of an ER evaluation: its value v and q >= the sum of the squares of
+// its monomials (coefficient times the product of its geometry values).
+struct EQ {
+    double v, q;
+};
+template <class T> struct BlockOf { using type = T; };
+template <> struct BlockOf<ER> { using type = EQ; };
 QA_HD double acc_zero(double*) { return 0.0; }
 QA_HD EBAcc acc_zero(EBAcc*) { return EBAcc{DD{0.0, 0.0}, 0.0}; }
 QA_HD DD acc_zero(DD*) { return DD{0.0, 0.0}; }
+QA_HD ERAcc acc_zero(ERAcc*) { return ERAcc{DD{0.0, 0.0}, 0.0}; }
 QA_HD void acc_add(double& s, double x) { s += x; }
 QA_HD void acc_add(EBAcc& s, EB x) {
 #pragma clang fp contract(off)
@@ -162,17 +210,36 @@ QA_HD void acc_add(EBAcc& s, EB x) {
     s.a += x.a;
 }
 QA_HD void acc_add(DD& s, DD x) { s = s + x; }
+QA_HD void acc_add(double& s, double x, int) { s += x; }
+QA_HD void acc_add(DD& s, DD x, int) { s = s + x; }
+QA_HD void acc_add(EBAcc& s, EB x, int) { acc_add(s, x); }
+QA_HD void acc_add(ERAcc& s, EQ x, int nb) {
+#pragma clang fp contract(off)
+    s.v = s.v + dd(x.v);
+    s.q += (double)nb * x.q;
+}
 QA_HD double acc_get(double s) { return s; }
 QA_HD EB acc_get(EBAcc s) { return EB{s.v.hi + s.v.lo, s.a}; }
 QA_HD DD acc_get(DD s) { return s; }
+QA_HD ER acc_get(ERAcc s) {
+    const double v = s.v.hi + s.v.lo;
+    return ER{v, s.q + v * v};
+}
 // division by the exact integer denominator of a table
 QA_HD double div_den(double x, double d) { return x / d; }
 QA_HD EB div_den(EB x, double d) { return EB{x.v / d, x.a / d}; }
 QA_HD DD div_den(DD x, double d) { return x / dd(d); }
+QA_HD ER div_den(ER x, double d) {
+    const double v = x.v / d;
+    return ER{v, x.q / (d * d) + v * v};
+}
 QA_HD double lift(double x, double*) { return x; }
 QA_HD EB lift(double x, EB*) { return EB{x, fabs(x)}; }
 QA_HD DD lift(DD x, DD*) { return x; }
+// a geometry value rounded from double-double to double: one rounding
+QA_HD ER lift(double x, ER*) { return ER{x, x * x}; }
 template <class T, class S> QA_HD T lift_to(S x) { return lift(x, (T*)nullptr); }
 template <> QA_HD double from_d<double>(double x) { return x; }
 template <> QA_HD EB from_d<EB>(double x) { return eb(x); }
 template <> QA_HD DD from_d<DD>(double x) { return dd(x); }
+template <> QA_HD ER from_d<ER>(double x) { return ER{x, 0.0}; }

@@ -57,7 +57,7 @@ struct DevTable {
 };
 
 struct DevBlock {
-    uint8_t k, r, pad0, pad1;
+    uint8_t k, r, cexp, pad1;              // cexp: 2^cexp >= max |coefficient| of the block
     uint32_t coef;                         // offset (in doubles) from the table's coef_off
     uint8_t bidx[QA_MAXK];                 // variable indices of the k pair factors
     uint8_t aidx[QA_MAXR];                 // variable indices of A for the r free slots

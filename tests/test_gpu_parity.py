@@ -89,6 +89,14 @@ def _eval_cmp(n, gis, npts, seed, gset=None):
             if residual:
                 assert i >= npts, ("an interior point needed more than double-double", gi, i)
             nres += int(residual)
+        # the probabilistic estimate (the batched form's flag) also covers the actual error
+        fe, ee, fle = P.eval_integrand(img, gi, zt, P.QA_FP64_EST)
+        sync()
+        fe, ee, fle = fe.cpu().numpy(), ee.cpu().numpy(), fle.cpu().numpy()
+        for i in range(len(zs)):
+            v = ref[i][0]
+            assert abs(fe[i] - v) <= ee[i] + 1e-12 * abs(v), (gi, i, fe[i], v, ee[i])
+            assert bool(fle[i]) == (not ee[i] <= 1e-11 * abs(fe[i]))
     return nres
 
 
@@ -126,6 +134,13 @@ def test_bound_covers_double_double(n):
         assert np.all(np.abs(fb - fd) <= eb + ed)
         assert np.array_equal(flag.astype(bool), ~(eb <= 1e-11 * np.abs(fb)))
         assert np.all(ed <= eb)
+        # the probabilistic estimate: covers the actual FP64 error, flags consistently
+        fe, ee, fle = P.eval_integrand(img, gi, zt, P.QA_FP64_EST)
+        sync()
+        fe, ee, fle = fe.cpu().numpy(), ee.cpu().numpy(), fle.cpu().numpy()
+        assert np.all(np.abs(fe - fd) <= ee + ed)
+        assert np.all(np.abs(fe - fb) <= ee + eb)
+        assert np.array_equal(fle.astype(bool), ~(ee <= 1e-11 * np.abs(fe)))
 
 
 def test_accumulate_compensated():
@@ -272,6 +287,12 @@ def test_eval_5loop_matches_oracle_golden():
             scale = abs(v) if v != 0 else pt["terms_abs"]
             assert abs(final[i] - v) <= 1e-10 * scale, (gi, i, final[i], v, flag[i], eb[i])
             assert abs(fb[i] - v) <= eb[i] + 1e-12 * abs(v), (gi, i, fb[i], v, eb[i])
+        fe, ee, _ = P.eval_integrand(img, gi, zt, P.QA_FP64_EST)
+        sync()
+        fe, ee = fe.cpu().numpy(), ee.cpu().numpy()
+        for i, pt in enumerate(gg["points"]):
+            v = pt["f"]
+            assert abs(fe[i] - v) <= ee[i] + 1e-12 * abs(v), (gi, i, fe[i], v, ee[i])
 
 
 def test_sample_and_eval_5loop_bench_stream():
@@ -303,14 +324,23 @@ def test_batched_5loop_matches_plain():
     for gi in (1, 40, 72):
         b = int(budgets[gi])
         z, lp, _ = P.sample_pdf(img, gi, 5, 0, 0, b)
-        fb, eb, flag = P.eval_integrand(img, gi, z, P.QA_FP64_BOUND)
+        fe, ee, flag = P.eval_integrand(img, gi, z, P.QA_FP64_EST)
         fd, _, _ = P.eval_integrand(img, gi, z, P.QA_DD)
         sync()
-        f = np.where(flag.cpu().numpy().astype(bool), fd.cpu().numpy(), fb.cpu().numpy())
-        w = f * np.exp(-lp.cpu().numpy())
-        good = np.isfinite(w)
+        fe, ee, flag, fd = fe.cpu().numpy(), ee.cpu().numpy(), flag.cpu().numpy().astype(bool), fd.cpu().numpy()
+        ip = np.exp(-lp.cpu().numpy())
+        # the batched selection: estimate on w against max(|w|, rms of the accurate weights)
+        w0 = fe * ip
+        good = np.isfinite(w0)
+        acc_ok = good & ~flag
+        scale = math.sqrt(math.fsum(w0[acc_ok] ** 2) / max(1, good.sum()))
+        need = flag & good & ~(ee * ip <= 1e-11 * np.maximum(np.abs(w0), scale))
+        w = np.where(need, fd, fe) * ip
         x = a[gi]
-        assert int(x["n"]) == good.sum() and int(x["n_flagged"]) == int(flag.cpu().numpy().sum())
+        assert int(x["n"]) == good.sum() and int(x["n_flagged"]) == int(need.sum())
         s1 = math.fsum(w[good])
         assert abs(x["s1_hi"] + x["s1_lo"] - s1) <= 1e-12 * math.fsum(np.abs(w[good]))
+        # every accepted FP64 weight is within 1e-10 of the scale of the double-double one
+        wd = fd * ip
+        assert np.all(np.abs(w[good] - wd[good]) <= 1e-10 * np.maximum(np.abs(wd[good]), scale))
     assert all(int(a[g]["n"]) == 0 for g in range(len(gs)) if g not in (1, 40, 72))
