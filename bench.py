@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--samples", type=int, default=1 << 23, help="samples per step over the 73 graphs")
-    ap.add_argument("--tile", type=int, default=1024)
+    ap.add_argument("--tile", type=int, default=256)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

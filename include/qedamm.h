@@ -154,9 +154,10 @@ int qa_accumulate(const double* f, const double* logp, uint64_t count, qa_acc* a
  * n_residual those whose double-double estimate still exceeds 1e-10 of that
  * scale.  Deterministic per-tile partials are reduced into acc (device, ng
  * records, overwritten).  The
- * work is split into rounds of 2048 tiles; one round is captured as a
- * hipGraph and replayed.  work (device) >= qa_work_bytes.  tile = multiple of
- * 64 (0 = 1024); grid = persistent waves (0 = 4 per CU, max 2048).
+ * work is split into rounds of at most 2^25 samples; one round is captured as
+ * a hipGraph and replayed.  work (device) >= qa_work_bytes (same budgets and
+ * tile; about 68 bytes per sample of a round).  tile = multiple of 64
+ * (0 = 256); grid = persistent waves (0 = 4 per CU, max 2048).
  * fused_ms (host, nullable): receives the summed duration of the fused
  * kernel over all rounds, from HIP events on `stream`. */
 int qa_work_bytes(const qa_set* s, const uint64_t* budgets, uint32_t tile, size_t* bytes);

@@ -52,7 +52,7 @@ template <> QA_HD void geo_scalar<DD, true>(DD& dst, const DD& x, double& cond) 
 // discrepancy in units of the double round-off, i.e. an estimate of the
 // polynomials' conditioning (the double-double error is about cond * 2^-104).
 template <class S, class T, int L, bool Cmp>
-QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& Uo, DD& Vo, double& cond) {
+QA_HD void geometry_L(const QA_RO DevPiece& pc, CLV<double> z, LV<S> vars, DD& Uo, DD& Vo, double& cond) {
     T U, V;
     const int nl = pc.nlines;
     T zl[QA_MAXL];
@@ -191,13 +191,13 @@ QA_HD void geometry_L(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& Uo, DD&
 
 // plain-double pass, then the double-double pass comparing against it
 template <class S, int L>
-QA_HD void geometry_2(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V, double& cond) {
+QA_HD void geometry_2(const QA_RO DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V, double& cond) {
     geometry_L<S, double, L, false>(pc, z, vars, U, V, cond);
     geometry_L<S, DD, L, true>(pc, z, vars, U, V, cond);
 }
 
 template <class S>
-QA_HD void geometry(const DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V, double& cond) {
+QA_HD void geometry(const QA_RO DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V, double& cond) {
     cond = 1.0;
     switch (pc.nchords) {
         case 1: geometry_2<S, 1>(pc, z, vars, U, V, cond); break;
@@ -217,15 +217,15 @@ template <int J> QA_HD constexpr int amap(int i) { return i + (i >= J ? 1 : 0); 
 // With Abs the leaves are |c[s]| (used with squared slot values for the
 // rounding-error estimate).
 template <class T, int R, int J, bool Abs = false> struct Fold {
-    QA_HD static T run(const double* c, const T* A) {
+    QA_HD static T run(const QA_RO double* c, const T* A) {
         return Fold<T, R - 1, J, Abs>::run(c, A) + A[amap<J>(R - 1)] * Fold<T, R - 1, J, Abs>::run(c + (1 << (R - 1)), A);
     }
 };
 template <class T, int J, bool Abs> struct Fold<T, 0, J, Abs> {
-    QA_HD static T run(const double* c, const T*) { return from_d<T>(Abs ? fabs(c[0]) : c[0]); }
+    QA_HD static T run(const QA_RO double* c, const T*) { return from_d<T>(Abs ? fabs(c[0]) : c[0]); }
 };
 
-template <class T, int J, bool Abs = false> QA_HD T fold(const double* c, const T* A, int r) {
+template <class T, int J, bool Abs = false> QA_HD T fold(const QA_RO double* c, const T* A, int r) {
     switch (r) {
         case 0: return Fold<T, 0, J, Abs>::run(c, A);
         case 1: return Fold<T, 1, J, Abs>::run(c, A);
@@ -254,7 +254,7 @@ template <class T, int J, bool Abs = false> QA_HD T fold(const double* c, const 
 
 // sum over the free slot j carrying the q-derivative: C_j * fold(others)
 template <class T, class S, int J> struct QTerms {
-    QA_HD static void run(T& s, const double* c, const T* A, int r, LV<S> vars, const DevBlock& b) {
+    QA_HD static void run(T& s, const QA_RO double* c, const T* A, int r, LV<S> vars, const QA_RO DevBlock& b) {
         if (J >= r) return;
         const int half = 1 << (r - 1);
         s = s + lift_to<T>(vars[b.cidx[J]]) * fold<T, J>(c + (1 << r) + J * half, A, r - 1);
@@ -262,12 +262,12 @@ template <class T, class S, int J> struct QTerms {
     }
 };
 template <class T, class S> struct QTerms<T, S, QA_MAXR> {
-    QA_HD static void run(T&, const double*, const T*, int, LV<S>, const DevBlock&) {}
+    QA_HD static void run(T&, const QA_RO double*, const T*, int, LV<S>, const QA_RO DevBlock&) {}
 };
 
 // one block: w * (Gamma_0 fold + Gamma_1 folds)
 template <class T, class S>
-QA_HD T eval_block(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
+QA_HD T eval_block(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars, bool has_q) {
     const int k = b.k, r = b.r;
     T w = from_d<T>(1.0);
 #pragma unroll
@@ -285,17 +285,17 @@ QA_HD T eval_block(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
 // statically sized block (R free slots, R <= QA_STATIC_R): fully unrolled folds
 #define QA_STATIC_R 6
 template <class T, class S, int R, int J> struct QStatic {
-    QA_HD static void run(T& s, const double* c, const T* A, LV<S> vars, const DevBlock& b) {
+    QA_HD static void run(T& s, const QA_RO double* c, const T* A, LV<S> vars, const QA_RO DevBlock& b) {
         s = s + lift_to<T>(vars[b.cidx[J]]) * Fold<T, R - 1, J>::run(c + (1 << R) + J * (1 << (R - 1)), A);
         QStatic<T, S, R, J + 1>::run(s, c, A, vars, b);
     }
 };
 template <class T, class S, int R> struct QStatic<T, S, R, R> {
-    QA_HD static void run(T&, const double*, const T*, LV<S>, const DevBlock&) {}
+    QA_HD static void run(T&, const QA_RO double*, const T*, LV<S>, const QA_RO DevBlock&) {}
 };
 
 template <class T, class S, int R>
-QA_HD T block_static(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
+QA_HD T block_static(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars, bool has_q) {
     const int k = b.k;
     T w = from_d<T>(1.0);
 #pragma unroll
@@ -312,10 +312,10 @@ QA_HD T block_static(const DevBlock& b, const double* c, LV<S> vars, bool has_q)
 
 // sum over the free slot j carrying the q-derivative, value and square folds
 template <class S, int J> struct QTermsQ {
-    QA_HD static void run(double& s, double& sq, const double* c, const double* A, const double* A2, int r, LV<S> vars,
-                          const DevBlock& b) {
+    QA_HD static void run(double& s, double& sq, const QA_RO double* c, const double* A, const double* A2, int r, LV<S> vars,
+                          const QA_RO DevBlock& b) {
         if (J >= r) return;
-        const double* cc = c + (1 << r) + J * (1 << (r - 1));
+        const QA_RO double* cc = c + (1 << r) + J * (1 << (r - 1));
         const double cj = vars[b.cidx[J]];
         s = s + cj * fold<double, J>(cc, A, r - 1);
         sq = sq + (cj * cj) * fold<double, J, true>(cc, A2, r - 1);
@@ -323,14 +323,14 @@ template <class S, int J> struct QTermsQ {
     }
 };
 template <class S> struct QTermsQ<S, QA_MAXR> {
-    QA_HD static void run(double&, double&, const double*, const double*, const double*, int, LV<S>, const DevBlock&) {}
+    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, int, LV<S>, const QA_RO DevBlock&) {}
 };
 
 // Block in EQ: the value, and q = 2^cexp * w^2 * sum_s |c_s| m_s^2 >= the sum
 // of squares of the block's monomials (m_s: product of the slot values of s;
 // 2^cexp >= max |c|).  Both folds share the coefficient loads.
 template <class S>
-QA_HD EQ eval_block_q(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
+QA_HD EQ eval_block_q(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars, bool has_q) {
     const int k = b.k, r = b.r;
     double w = 1.0;
 #pragma unroll
@@ -350,21 +350,21 @@ QA_HD EQ eval_block_q(const DevBlock& b, const double* c, LV<S> vars, bool has_q
 }
 
 template <class S, int R, int J> struct QStaticQ {
-    QA_HD static void run(double& s, double& sq, const double* c, const double* A, const double* A2, LV<S> vars,
-                          const DevBlock& b) {
+    QA_HD static void run(double& s, double& sq, const QA_RO double* c, const double* A, const double* A2, LV<S> vars,
+                          const QA_RO DevBlock& b) {
         const double cj = vars[b.cidx[J]];
-        const double* cc = c + (1 << R) + J * (1 << (R - 1));
+        const QA_RO double* cc = c + (1 << R) + J * (1 << (R - 1));
         s = s + cj * Fold<double, R - 1, J>::run(cc, A);
         sq = sq + (cj * cj) * Fold<double, R - 1, J, true>::run(cc, A2);
         QStaticQ<S, R, J + 1>::run(s, sq, c, A, A2, vars, b);
     }
 };
 template <class S, int R> struct QStaticQ<S, R, R> {
-    QA_HD static void run(double&, double&, const double*, const double*, const double*, LV<S>, const DevBlock&) {}
+    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, LV<S>, const QA_RO DevBlock&) {}
 };
 
 template <class S, int R>
-QA_HD EQ block_static_q(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
+QA_HD EQ block_static_q(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars, bool has_q) {
     const int k = b.k;
     double w = 1.0;
 #pragma unroll
@@ -383,7 +383,7 @@ QA_HD EQ block_static_q(const DevBlock& b, const double* c, LV<S> vars, bool has
     return EQ{w * s, ldexp(w * w * sq, b.cexp)};
 }
 template <class T, class S, int R>
-QA_HD T block_any(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
+QA_HD T block_any(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars, bool has_q) {
     if constexpr (std::is_same<T, EQ>::value) return block_static_q<S, R>(b, c, vars, has_q);
     else return block_static<T, S, R>(b, c, vars, has_q);
 }
@@ -393,11 +393,11 @@ QA_HD T block_any(const DevBlock& b, const double* c, LV<S> vars, bool has_q) {
 // (k + R lifted geometry values, the R-level fold, the k-pair product, the
 // final product), which acc_add uses for the ER estimate.
 template <class T, class S, int R, class AT>
-QA_HD void group_static(const DevBlock* blocks, int b0, int b1, const double* coefs, LV<S> vars, bool hq, AT& acc) {
+QA_HD void group_static(const QA_RO DevBlock* blocks, int b0, int b1, const QA_RO double* coefs, LV<S> vars, bool hq, AT& acc) {
     int bi = b0;
     for (; bi + 1 < b1; bi += 2) {
-        const DevBlock& x = blocks[bi];
-        const DevBlock& y = blocks[bi + 1];
+        const QA_RO DevBlock& x = blocks[bi];
+        const QA_RO DevBlock& y = blocks[bi + 1];
         const T vx = block_any<T, S, R>(x, coefs + x.coef, vars, hq);
         const T vy = block_any<T, S, R>(y, coefs + y.coef, vars, hq);
         acc_add(acc, vx, 2 * (x.k + R) + 3);
@@ -409,16 +409,19 @@ QA_HD void group_static(const DevBlock* blocks, int b0, int b1, const double* co
 // Evaluate one coefficient table: poly[k] = (1/denom) * sum over blocks with k
 // pairs.  All blocks with the same k have the same number of free slots r.
 template <class T, class S>
-QA_HD void eval_table(const uint8_t* __restrict__ img, const DevTable& tb, LV<S> vars, int n, T* poly) {
+QA_HD void eval_table(const QA_RO uint8_t* img, const QA_RO DevTable& tb, LV<S> vars, int n, T* poly,
+                      int slice = 0, int nslices = 1) {
     using AT = typename Acc<T>::type;
     using BT = typename BlockOf<T>::type;
-    const DevBlock* blocks = reinterpret_cast<const DevBlock*>(img + tb.hdr_off);
-    const double* coefs = reinterpret_cast<const double*>(img + tb.coef_off);
+    const QA_RO DevBlock* blocks = reinterpret_cast<const QA_RO DevBlock*>(img + tb.hdr_off);
+    const QA_RO double* coefs = reinterpret_cast<const QA_RO double*>(img + tb.coef_off);
     const bool hq = tb.has_q != 0;
 #pragma unroll
     for (int k = 0; k < QA_MAXN; ++k) {
         AT acc = acc_zero((AT*)nullptr);
-        const int b0 = tb.kstart[k], b1 = tb.kstart[k + 1];
+        // slice `slice` of nslices: a contiguous share of each k-range
+        const int k0 = tb.kstart[k], k1 = tb.kstart[k + 1];
+        const int b0 = k0 + (k1 - k0) * slice / nslices, b1 = k0 + (k1 - k0) * (slice + 1) / nslices;
         if (k < n && b0 < b1) {
             // the double-double path (flagged points only) uses the compact generic loop
             const int rsel = std::is_same<T, DD>::value ? -1 : blocks[b0].r;
@@ -432,7 +435,7 @@ QA_HD void eval_table(const uint8_t* __restrict__ img, const DevTable& tb, LV<S>
                 case 6: group_static<BT, S, 6>(blocks, b0, b1, coefs, vars, hq, acc); break;
                 default:
                     for (int bi = b0; bi < b1; ++bi) {
-                        const DevBlock& b = blocks[bi];
+                        const QA_RO DevBlock& b = blocks[bi];
                         if constexpr (std::is_same<BT, EQ>::value)
                             acc_add(acc, eval_block_q<S>(b, coefs + b.coef, vars, hq), 2 * (b.k + b.r) + 3);
                         else
@@ -467,29 +470,33 @@ QA_HD double kcoef(int n, int K) {
 }
 
 // f_G(z) at one point.  z: the M line parameters, used as given (f is
-// homogeneous of degree -M).  Returns f; for EB the magnitude carries the
+// homogeneous of degree -M).  f is linear in the coefficient table of the
+// last (whole-graph) piece of each term: with nslices > 1 only the share
+// `slice` of those tables' blocks is summed, and the nslices partial results
+// add up to f (the double-double pass splits a point over several waves).  Returns f; for EB the magnitude carries the
 // rounding-error scale; cond_out = worst conditioning of the graph
 // polynomials seen (loop-matrix pivot ratio, cancellation ratios of flows and
 // contraction coefficients), which bounds their relative error in units of
 // the double-double round-off.
 template <class T>
-QA_HD T eval_point(const uint8_t* __restrict__ img, const DevGraph& G, CLV<double> z,
-                   LV<typename GeoOf<T>::type> vars, LV<T> polys, double& cond_out) {
+QA_HD T eval_point(const QA_RO uint8_t* img, const QA_RO DevGraph& G, CLV<double> z,
+                   LV<typename GeoOf<T>::type> vars, LV<T> polys, double& cond_out, int slice = 0,
+                   int nslices = 1) {
     using S = typename GeoOf<T>::type;
     const int n = G.n;
-    const DevTerm* terms = reinterpret_cast<const DevTerm*>(img + G.terms_off);
+    const QA_RO DevTerm* terms = reinterpret_cast<const QA_RO DevTerm*>(img + G.terms_off);
     T f = from_d<T>(0.0);
     double cond_max = 1.0;
     double scale_n = 1.0;
     for (int i = 0; i < n; ++i) scale_n *= 0.25;
     for (int ti = 0; ti < G.nterms; ++ti) {
-        const DevTerm& tm = terms[ti];
-        const DevPiece* pcs = reinterpret_cast<const DevPiece*>(img + tm.pieces_off);
+        const QA_RO DevTerm& tm = terms[ti];
+        const QA_RO DevPiece* pcs = reinterpret_cast<const QA_RO DevPiece*>(img + tm.pieces_off);
         T pref = from_d<T>(1.0);
         T Vt = from_d<T>(0.0);
         T top[QA_MAXN];
         for (int pi = 0; pi < tm.npieces; ++pi) {
-            const DevPiece& pc = pcs[pi];
+            const QA_RO DevPiece& pc = pcs[pi];
             DD Ud, Vd;
             double cond;
             geometry<S>(pc, z, vars, Ud, Vd, cond);
@@ -502,7 +509,7 @@ QA_HD T eval_point(const uint8_t* __restrict__ img, const DevGraph& G, CLV<doubl
             Vt = Vt + V;
             const int nins = pc.nins;
             const int nop = pc.op == QA_OP_US ? 2 : 1;
-            const DevTable* tabs = reinterpret_cast<const DevTable*>(img + pc.tab_off);
+            const QA_RO DevTable* tabs = reinterpret_cast<const QA_RO DevTable*>(img + pc.tab_off);
             T res[2][QA_MAXN];
 #pragma unroll
             for (int opv = 0; opv < 2; ++opv) {
@@ -512,7 +519,10 @@ QA_HD T eval_point(const uint8_t* __restrict__ img, const DevGraph& G, CLV<doubl
                 for (int k = 0; k < QA_MAXN; ++k) acc[k] = from_d<T>(0.0);
                 for (int var = 0; var < (1 << nins); ++var) {
                     T P[QA_MAXN];
-                    eval_table<T, S>(img, tabs[(opv << nins) + var], vars, n, P);
+                    if (pi + 1 == tm.npieces)
+                        eval_table<T, S>(img, tabs[(opv << nins) + var], vars, n, P, slice, nslices);
+                    else
+                        eval_table<T, S>(img, tabs[(opv << nins) + var], vars, n, P);
                     for (int t = 0; t < nins; ++t) {
                         T ch[QA_MAXN];
                         const int s = pc.ins_slot[t] + ((var >> t) & 1);

@@ -55,7 +55,7 @@ struct Stream {
 // sector-tree sampling from eq. (1): choose j_1..j_M with P(j | S) =
 // W(S\j) / sum_j' W(S\j'), then t_l ~ Exp(Deg(S_l)) and ln z_{j_l} = -sum t.
 // Writes z (normalised) through zv, returns log p; order[l] = j_(l+1).
-__device__ __forceinline__ bool sample_point(const double* __restrict__ D, const double* __restrict__ W, int M, const Stream& st,
+__device__ __forceinline__ bool sample_point(const QA_RO double* D, const QA_RO double* W, int M, const Stream& st,
                              LV<double> zv, double& logp, uint8_t* order, double* tl) {
     const uint32_t full = (1u << M) - 1;
     uint32_t S = full;
@@ -117,19 +117,20 @@ __device__ __forceinline__ bool sample_point(const double* __restrict__ D, const
     return ok && isfinite(logp);
 }
 
-__device__ __forceinline__ const DevGraph& dev_graph(const uint8_t* img, uint32_t g) {
-    const DevHeader* h = reinterpret_cast<const DevHeader*>(img);
-    return reinterpret_cast<const DevGraph*>(img + h->graphs_off)[g];
+__device__ __forceinline__ const QA_RO DevGraph& dev_graph(const QA_RO uint8_t* img, uint32_t g) {
+    const QA_RO DevHeader* h = reinterpret_cast<const QA_RO DevHeader*>(img);
+    return reinterpret_cast<const QA_RO DevGraph*>(img + h->graphs_off)[g];
 }
 
-__global__ void __launch_bounds__(256) k_sample(const uint8_t* __restrict__ img, uint32_t graph, uint2 key,
+__global__ void __launch_bounds__(256) k_sample(const uint8_t* __restrict__ img_, uint32_t graph, uint2 key,
                                                 uint64_t first, uint64_t count, double* __restrict__ z,
                                                 double* __restrict__ logp, uint8_t* __restrict__ sector) {
+    const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const DevGraph& G = dev_graph(img, graph);
-    const double* D = reinterpret_cast<const double*>(img + G.deg_off);
-    const double* W = reinterpret_cast<const double*>(img + G.w_off);
+    const QA_RO DevGraph& G = dev_graph(img, graph);
+    const QA_RO double* D = reinterpret_cast<const QA_RO double*>(img + G.deg_off);
+    const QA_RO double* W = reinterpret_cast<const QA_RO double*>(img + G.w_off);
     Stream st{key, graph, first + i};
     uint8_t order[QA_MAXM];
     double tl[QA_MAXM];
@@ -186,25 +187,27 @@ __device__ __forceinline__ double est_dd(double q, double cond, double f) {
     return 0x1p-104 * sqrt(q) * (40.0 + 256.0 * cond) + QA_U * fabs(f);
 }
 
-__global__ void __launch_bounds__(64) k_eval_fp64(const uint8_t* __restrict__ img, uint32_t graph,
+__global__ void __launch_bounds__(64) k_eval_fp64(const uint8_t* __restrict__ img_, uint32_t graph,
                                                   const double* __restrict__ z, uint64_t count, double* __restrict__ f) {
+    const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     extern __shared__ char lds[];
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const DevGraph& G = dev_graph(img, graph);
+    const QA_RO DevGraph& G = dev_graph(img, graph);
     LV<double> vars, polys;
     lane_views<double>(lds, G.npoly, vars, polys);
     double cond;
     f[i] = eval_point<double>(img, G, CLV<double>{z + i, (int)count}, vars, polys, cond);
 }
 
-__global__ void __launch_bounds__(64) k_eval_bound(const uint8_t* __restrict__ img, uint32_t graph,
+__global__ void __launch_bounds__(64) k_eval_bound(const uint8_t* __restrict__ img_, uint32_t graph,
                                                    const double* __restrict__ z, uint64_t count, double* __restrict__ f,
                                                    double* __restrict__ err, uint8_t* __restrict__ flag) {
+    const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     extern __shared__ char lds[];
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const DevGraph& G = dev_graph(img, graph);
+    const QA_RO DevGraph& G = dev_graph(img, graph);
     LV<double> vars;
     LV<EB> polys;
     lane_views<EB>(lds, G.npoly, vars, polys);
@@ -216,13 +219,14 @@ __global__ void __launch_bounds__(64) k_eval_bound(const uint8_t* __restrict__ i
     if (flag) flag[i] = !(e <= 1e-11 * fabs(r.v));
 }
 
-__global__ void __launch_bounds__(64) k_eval_est(const uint8_t* __restrict__ img, uint32_t graph,
+__global__ void __launch_bounds__(64) k_eval_est(const uint8_t* __restrict__ img_, uint32_t graph,
                                                  const double* __restrict__ z, uint64_t count, double* __restrict__ f,
                                                  double* __restrict__ err, uint8_t* __restrict__ flag) {
+    const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     extern __shared__ char lds[];
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const DevGraph& G = dev_graph(img, graph);
+    const QA_RO DevGraph& G = dev_graph(img, graph);
     LV<double> vars;
     LV<ER> polys;
     lane_views<ER>(lds, G.npoly, vars, polys);
@@ -234,13 +238,14 @@ __global__ void __launch_bounds__(64) k_eval_est(const uint8_t* __restrict__ img
     if (flag) flag[i] = !(e <= 1e-11 * fabs(r.v));
 }
 
-__global__ void __launch_bounds__(64) k_eval_dd(const uint8_t* __restrict__ img, uint32_t graph,
+__global__ void __launch_bounds__(64) k_eval_dd(const uint8_t* __restrict__ img_, uint32_t graph,
                                                 const double* __restrict__ z, uint64_t count, double* __restrict__ f,
                                                 double* __restrict__ err) {
+    const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     extern __shared__ char lds[];
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const DevGraph& G = dev_graph(img, graph);
+    const QA_RO DevGraph& G = dev_graph(img, graph);
     double cond = 1.0, cond_dd;
     double mag = 0.0;
     if (err) {   // magnitude pass for the bound
@@ -338,6 +343,7 @@ struct FlagEntry {
     double w;         // FP64 weight f / p
     double estw;      // FP64 error estimate of w
     double q, cond;   // ER variance and geometry conditioning of the FP64 pass
+    double ip;        // 1 / p
     double c1, c2;    // corrections written by the double-double pass
     uint32_t graph;
     uint8_t fixed;    // recomputed in double-double
@@ -345,7 +351,7 @@ struct FlagEntry {
     uint8_t pad[2];
 };
 struct Work {
-    uint32_t* counter;       // [0] tile queue, [1] round, [2] selected entries, [3] fix chunk queue
+    uint32_t* counter;       // [0..7] tile queues (one per XCD), [8] round, [9] selected entries, [10] fix chunks
     uint64_t* gtile0;        // per graph: first global tile index (ng + 1 entries)
     uint64_t* budget;        // per graph samples
     Partial* partial;        // per round-tile
@@ -355,11 +361,24 @@ struct Work {
     uint32_t* nsel;          // per round-tile: entries selected for double-double
     uint32_t* seloff;        // per round-tile: offset of its selected entries
     uint32_t* sel;           // selected entry indices (t * tile + e), tile order
+    DD* fpart;               // double-double pass: partial f per (selected entry, slice)
+    double* fcond;           // double-double pass: geometry conditioning per selected entry
+    uint32_t grid;           // persistent waves of the double-double pass
     double* zbuf;            // per persistent wave: QA_MAXM * 64
     uint32_t tile, per_round, ng;
     uint64_t ntiles;
     uint64_t first;
 };
+
+constexpr uint32_t kQueues = 8;   // one tile queue per XCD (L2 domain)
+enum { kCRound = 8, kCSel = 9, kCFix = 10, kCSlices = 11 };
+
+// first round-tile and number of tiles of the current round
+__device__ __forceinline__ uint32_t round_len(const Work& w, uint64_t& t0) {
+    t0 = (uint64_t)w.counter[kCRound] * w.per_round;
+    const uint64_t left = w.ntiles - t0;
+    return (uint32_t)(left < w.per_round ? left : w.per_round);
+}
 
 __device__ __forceinline__ void tile_of(const Work& w, uint64_t gt, uint32_t& g, uint64_t& s0, uint32_t& cnt) {
     uint32_t lo = 0, hi = w.ng;
@@ -376,49 +395,55 @@ __device__ __forceinline__ void tile_of(const Work& w, uint64_t gt, uint32_t& g,
 
 // round-tile range [a, b) of graph g in the current round
 __device__ __forceinline__ bool round_tiles(const Work& w, uint32_t g, uint64_t& a, uint64_t& b, uint64_t& t0) {
-    const uint64_t round = w.counter[1];
-    t0 = round * w.per_round;
-    const uint64_t t1 = t0 + w.per_round;
+    const uint32_t nr = round_len(w, t0);
+    const uint64_t t1 = t0 + nr;
     a = w.gtile0[g] > t0 ? w.gtile0[g] : t0;
     b = w.gtile0[g + 1] < t1 ? w.gtile0[g + 1] : t1;
     return a < b;
 }
 
 __global__ void k_reset(Work w) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) w.counter[0] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kQueues) w.counter[threadIdx.x] = 0;
 }
 __global__ void k_next_round(Work w) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) w.counter[1] += 1;
+    if (threadIdx.x == 0 && blockIdx.x == 0) w.counter[kCRound] += 1;
 }
 
 // Fused pass: sample, evaluate in FP64 with the ER estimate, accumulate w and
 // w^2 per tile, and list the points whose estimate exceeds 1e-11 |f|
 // (candidates for the double-double pass).
-__global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, uint2 key, Work w) {
+__global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img_, uint2 key, Work w) {
+    const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     extern __shared__ char lds[];
     const int lane = threadIdx.x;
     LV<double> vars;
     LV<ER> polys;
     lane_views<ER>(lds, 0, vars, polys);
     double* zb = w.zbuf + (uint64_t)blockIdx.x * QA_MAXM * 64;
-    const uint64_t round = w.counter[1];
-    for (;;) {
+    uint64_t rt0;
+    const uint32_t nr = round_len(w, rt0);
+    // The round's tiles (graph-major) are split into kQueues contiguous ranges.
+    // Workgroups are dispatched to the XCDs round-robin, so the waves of one
+    // XCD share a range, and with it the coefficient tables in their L2; a
+    // wave whose range is drained helps the following ones.
+    const uint32_t x0 = blockIdx.x % kQueues;
+    for (uint32_t k = 0; k < kQueues; ++k) {
+      const uint32_t x = (x0 + k) % kQueues;
+      const uint32_t qlo = (uint32_t)((uint64_t)nr * x / kQueues), qhi = (uint32_t)((uint64_t)nr * (x + 1) / kQueues);
+      for (;;) {
         uint32_t t = 0;
-        if (lane == 0) t = atomicAdd(w.counter, 1u);
-        t = __shfl(t, 0);
-        if (t >= w.per_round) break;
-        const uint64_t gt = round * w.per_round + t;
+        if (lane == 0) t = atomicAdd(w.counter + x, 1u);
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));   // wave-uniform: scalar registers, scalar loads
+        if (t >= qhi - qlo) break;
+        t += qlo;
+        const uint64_t gt = rt0 + t;
         Partial pr{};
-        if (gt >= w.ntiles) {
-            if (lane == 0) { w.partial[t] = pr; w.nflag[t] = 0; }
-            continue;
-        }
         uint32_t g, cnt;
         uint64_t s0;
         tile_of(w, gt, g, s0, cnt);
-        const DevGraph& G = dev_graph(img, g);
-        const double* D = reinterpret_cast<const double*>(img + G.deg_off);
-        const double* W = reinterpret_cast<const double*>(img + G.w_off);
+        const QA_RO DevGraph& G = dev_graph(img, g);
+        const QA_RO double* D = reinterpret_cast<const QA_RO double*>(img + G.deg_off);
+        const QA_RO double* W = reinterpret_cast<const QA_RO double*>(img + G.w_off);
         DD s1{0, 0}, s2{0, 0};
         double s2g = 0.0;
         uint64_t n = 0, bad = 0;
@@ -426,7 +451,7 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
         for (uint32_t base = 0; base < cnt; base += 64) {
             const uint32_t j = base + lane;
             const bool act = j < cnt;
-            double wv = 0.0, ew = 0.0, qv = 0.0, cnd = 1.0;
+            double wv = 0.0, ew = 0.0, qv = 0.0, cnd = 1.0, ipv = 0.0;
             bool flagged = false, good = false;
             if (act) {
                 Stream st{key, g, s0 + j};
@@ -444,6 +469,7 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
                     cnd = cond;
                     wv = r.v * ip;
                     ew = e * ip;
+                    ipv = ip;
                     good = isfinite(wv);
                     flagged = good && !(e <= 1e-11 * fabs(r.v));
                 }
@@ -465,6 +491,7 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
                 fe.estw = ew;
                 fe.q = qv;
                 fe.cond = cnd;
+                fe.ip = ipv;
                 fe.c1 = 0.0;
                 fe.c2 = 0.0;
                 fe.graph = g;
@@ -485,24 +512,30 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img, u
             w.partial[t] = pr;
             w.nflag[t] = nfl;
         }
+      }
     }
 }
 
 // Per graph: the scale of its weights, sqrt(sum w^2 / N) over the accurate
 // weights of earlier rounds and the points of this round that passed the
 // relative test (a lower bound of the rms weight).
-__global__ void k_scale(Work w, const qa_acc* __restrict__ acc) {
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= w.ng) return;
+__global__ void __launch_bounds__(64) k_scale(Work w, const qa_acc* __restrict__ acc) {
+    const uint32_t g = blockIdx.x, lane = threadIdx.x;
     uint64_t a, b, t0;
-    if (!round_tiles(w, g, a, b, t0)) return;
-    double s2 = acc[g].s2_hi + acc[g].s2_lo;
-    uint64_t n = acc[g].n;
-    for (uint64_t gt = a; gt < b; ++gt) {
+    if (g >= w.ng || !round_tiles(w, g, a, b, t0)) return;
+    double s2 = 0.0;
+    uint64_t n = 0;
+    for (uint64_t gt = a + lane; gt < b; gt += 64) {
         s2 += w.partial[gt - t0].s2g;
         n += w.partial[gt - t0].n;
     }
-    w.scale[g] = n ? sqrt(s2 / (double)n) : 0.0;
+    s2 = wave_sum_f64(s2);
+    n = wave_sum_u64(n);
+    if (lane == 0) {
+        s2 += acc[g].s2_hi + acc[g].s2_lo;
+        n += acc[g].n;
+        w.scale[g] = n ? sqrt(s2 / (double)n) : 0.0;
+    }
 }
 
 // A candidate is recomputed in double-double when its error estimate on w
@@ -513,7 +546,9 @@ __device__ __forceinline__ bool needs_dd(const FlagEntry& fe, const double* scal
 
 __global__ void __launch_bounds__(64) k_select(Work w) {
     const int lane = threadIdx.x;
-    for (uint32_t t = blockIdx.x; t < w.per_round; t += gridDim.x) {
+    uint64_t rt0;
+    const uint32_t nr = round_len(w, rt0);
+    for (uint32_t t = blockIdx.x; t < nr; t += gridDim.x) {
         const uint32_t nf = w.nflag[t];
         uint32_t cnt = 0;
         for (uint32_t b = 0; b < nf; b += 64) {
@@ -530,11 +565,14 @@ __global__ void __launch_bounds__(64) k_select(Work w) {
     }
 }
 
-// exclusive prefix sum of nsel over the round's tiles (one wave)
-__global__ void __launch_bounds__(64) k_scan(Work w) {
-    const uint32_t lane = threadIdx.x;
-    const uint32_t per = (w.per_round + 63) / 64;
-    const uint32_t t0 = lane * per, t1 = t0 + per < w.per_round ? t0 + per : w.per_round;
+// exclusive prefix sum of nsel over the round's tiles (one block of 1024)
+__global__ void __launch_bounds__(1024) k_scan(Work w) {
+    __shared__ uint32_t wsum[16];
+    const uint32_t tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    uint64_t rt0;
+    const uint32_t nr = round_len(w, rt0);
+    const uint32_t per = (nr + 1023) / 1024;
+    const uint32_t t0 = tid * per < nr ? tid * per : nr, t1 = t0 + per < nr ? t0 + per : nr;
     uint32_t loc = 0;
     for (uint32_t t = t0; t < t1; ++t) loc += w.nsel[t];
     uint32_t inc = loc;
@@ -543,20 +581,39 @@ __global__ void __launch_bounds__(64) k_scan(Work w) {
         const uint32_t o = __shfl_up(inc, d);
         if ((int)lane >= d) inc += o;
     }
-    uint32_t off = inc - loc;
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t v = wsum[i];
+            wsum[i] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    uint32_t off = wsum[wave] + inc - loc;
     for (uint32_t t = t0; t < t1; ++t) {
         w.seloff[t] = off;
         off += w.nsel[t];
     }
-    if (lane == 63) {
-        w.counter[2] = inc;
-        w.counter[3] = 0;
+    if (tid == 1023) {
+        // the double-double pass splits each chunk of 64 entries into slices so
+        // that chunks x slices fills its waves
+        const uint32_t nchunks = (off + 63) / 64;
+        uint32_t ns = nchunks ? w.grid / nchunks : 1;
+        ns = ns < 1 ? 1 : (ns > 64 ? 64 : ns);
+        w.counter[kCSel] = off;
+        w.counter[kCFix] = 0;
+        w.counter[kCSlices] = ns;
     }
 }
 
 __global__ void __launch_bounds__(64) k_compact(Work w) {
     const int lane = threadIdx.x;
-    for (uint32_t t = blockIdx.x; t < w.per_round; t += gridDim.x) {
+    uint64_t rt0;
+    const uint32_t nr = round_len(w, rt0);
+    for (uint32_t t = blockIdx.x; t < nr; t += gridDim.x) {
         const uint32_t nf = w.nflag[t];
         uint32_t pos = w.seloff[t];
         for (uint32_t b = 0; b < nf; b += 64) {
@@ -570,98 +627,127 @@ __global__ void __launch_bounds__(64) k_compact(Work w) {
 }
 
 // Double-double recompute of the selected entries: persistent waves take
-// chunks of 64 consecutive entries (graph-major order); a chunk that spans
-// graphs is processed one graph at a time.
-__global__ void __launch_bounds__(64) k_fix_dd(const uint8_t* __restrict__ img, uint2 key, Work w) {
+// items (chunk of 64 consecutive entries in graph-major order, slice of the
+// whole-graph coefficient tables); a chunk that spans graphs is processed one
+// graph at a time.  Each item writes its partial f; k_fix_combine adds the
+// slices in order.
+__global__ void __launch_bounds__(64) k_fix_dd(const uint8_t* __restrict__ img_, uint2 key, Work w) {
+    const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     extern __shared__ char lds[];
     const int lane = threadIdx.x;
     LV<DD> vars, polys;
     lane_views<DD>(lds, 0, vars, polys);
     double* zb = w.zbuf + (uint64_t)blockIdx.x * QA_MAXM * 64;
-    const uint32_t total = w.counter[2];
+    const uint32_t total = w.counter[kCSel], ns = w.counter[kCSlices];
+    const uint32_t items = (total + 63) / 64 * ns;
     for (;;) {
-        uint32_t c = 0;
-        if (lane == 0) c = atomicAdd(w.counter + 3, 1u);
-        c = __shfl(c, 0);
-        if ((uint64_t)c * 64 >= total) break;
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(w.counter + kCFix, 1u);
+        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
+        if (it >= items) break;
+        const uint32_t c = it / ns, j = it % ns;
         const uint32_t idx = c * 64 + lane;
         const bool act = idx < total;
-        FlagEntry* fe = act ? &w.flags[w.sel[idx]] : nullptr;
+        const FlagEntry* fe = act ? &w.flags[w.sel[idx]] : nullptr;
         const uint32_t mine = act ? fe->graph : 0xffffffffu;
         bool done = !act;
         for (;;) {
-            const uint32_t g = wave_min_u32(done ? 0xffffffffu : mine);
+            const uint32_t g = __builtin_amdgcn_readfirstlane(wave_min_u32(done ? 0xffffffffu : mine));
             if (g == 0xffffffffu) break;
             if (!done && mine == g) {
-                const DevGraph& G = dev_graph(img, g);
-                const double* D = reinterpret_cast<const double*>(img + G.deg_off);
-                const double* W = reinterpret_cast<const double*>(img + G.w_off);
+                const QA_RO DevGraph& G = dev_graph(img, g);
+                const QA_RO double* D = reinterpret_cast<const QA_RO double*>(img + G.deg_off);
+                const QA_RO double* W = reinterpret_cast<const QA_RO double*>(img + G.w_off);
                 Stream st{key, g, fe->sample};
                 uint8_t order[QA_MAXM];
                 double tl[QA_MAXM], lp, cond;
                 LV<double> zv{zb + lane, 64};
                 sample_point(D, W, G.M, st, zv, lp, order, tl);
-                DD r = eval_point<DD>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond);
-                const double fdd = r.hi + r.lo;
-                const double ip = exp(-lp);
-                fe->residual = !(est_dd(fe->q, fmax(cond, fe->cond), fdd) * ip <=
-                                 1e-10 * fmax(fabs(fdd) * ip, w.scale[g]));
-                const DD wd = r * ip;
-                const DD d1 = wd - dd(fe->w);
-                const DD d2 = wd * wd - two_prod(fe->w, fe->w);
-                fe->c1 = d1.hi + d1.lo;
-                fe->c2 = d2.hi + d2.lo;
+                const DD r = eval_point<DD>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond, (int)j, (int)ns);
+                w.fpart[(uint64_t)idx * ns + j] = r;
+                if (j == 0) w.fcond[idx] = cond;
                 done = true;
             }
         }
     }
 }
 
-// per graph, in tile order: partials then corrections -> acc
-__global__ void k_reduce(Work w, qa_acc* acc) {
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= w.ng) return;
+// per selected entry: f = sum of its slices (in order); corrections of w and
+// w^2 and the residual test
+__global__ void __launch_bounds__(256) k_fix_combine(Work w) {
+    const uint32_t total = w.counter[kCSel], ns = w.counter[kCSlices];
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        FlagEntry& fe = w.flags[w.sel[e]];
+        DD r{0.0, 0.0};
+        for (uint32_t j = 0; j < ns; ++j) r = r + w.fpart[(uint64_t)e * ns + j];
+        const double fdd = r.hi + r.lo, ip = fe.ip;
+        fe.residual = !(est_dd(fe.q, fmax(w.fcond[e], fe.cond), fdd) * ip <=
+                        1e-10 * fmax(fabs(fdd) * ip, w.scale[fe.graph]));
+        const DD wd = r * ip;
+        const DD d1 = wd - dd(fe.w);
+        const DD d2 = wd * wd - two_prod(fe.w, fe.w);
+        fe.c1 = d1.hi + d1.lo;
+        fe.c2 = d2.hi + d2.lo;
+    }
+}
+
+// per graph (one wave): the round's partials and the corrections of its
+// selected entries -> acc, in a fixed order
+__global__ void __launch_bounds__(64) k_reduce(Work w, qa_acc* acc) {
+    const uint32_t g = blockIdx.x, lane = threadIdx.x;
     uint64_t a, b, t0;
-    if (!round_tiles(w, g, a, b, t0)) return;
-    DD s1{acc[g].s1_hi, acc[g].s1_lo}, s2{acc[g].s2_hi, acc[g].s2_lo};
-    uint64_t n = acc[g].n, nf = acc[g].n_flagged, nb = acc[g].n_bad, nr = acc[g].n_residual;
-    for (uint64_t gt = a; gt < b; ++gt) {
-        const uint32_t t = (uint32_t)(gt - t0);
-        const Partial& p = w.partial[t];
+    if (g >= w.ng || !round_tiles(w, g, a, b, t0)) return;
+    DD s1{0.0, 0.0}, s2{0.0, 0.0};
+    uint64_t n = 0, nb = 0, nr = 0;
+    for (uint64_t gt = a + lane; gt < b; gt += 64) {
+        const Partial& p = w.partial[gt - t0];
         s1 = s1 + DD{p.s1_hi, p.s1_lo};
         s2 = s2 + DD{p.s2_hi, p.s2_lo};
         n += p.n;
         nb += p.nbad;
-        for (uint32_t e = 0; e < w.nflag[t]; ++e) {
-            const FlagEntry& fe = w.flags[(uint64_t)t * w.tile + e];
-            if (!fe.fixed) continue;
-            s1 = s1 + dd(fe.c1);
-            s2 = s2 + dd(fe.c2);
-            nr += fe.residual;
-            ++nf;
-        }
     }
-    acc[g].s1_hi = s1.hi; acc[g].s1_lo = s1.lo;
-    acc[g].s2_hi = s2.hi; acc[g].s2_lo = s2.lo;
-    acc[g].n = n; acc[g].n_flagged = nf; acc[g].n_bad = nb; acc[g].n_residual = nr;
+    // the selected entries of graph g are contiguous in sel (tile order)
+    const uint32_t e0 = w.seloff[a - t0], e1 = w.seloff[b - 1 - t0] + w.nsel[b - 1 - t0];
+    for (uint32_t e = e0 + lane; e < e1; e += 64) {
+        const FlagEntry& fe = w.flags[w.sel[e]];
+        s1 = s1 + dd(fe.c1);
+        s2 = s2 + dd(fe.c2);
+        nr += fe.residual;
+    }
+    s1 = wave_sum_dd(s1);
+    s2 = wave_sum_dd(s2);
+    n = wave_sum_u64(n);
+    nb = wave_sum_u64(nb);
+    nr = wave_sum_u64(nr);
+    if (lane == 0) {
+        s1 = DD{acc[g].s1_hi, acc[g].s1_lo} + s1;
+        s2 = DD{acc[g].s2_hi, acc[g].s2_lo} + s2;
+        acc[g].s1_hi = s1.hi; acc[g].s1_lo = s1.lo;
+        acc[g].s2_hi = s2.hi; acc[g].s2_lo = s2.lo;
+        acc[g].n += n;
+        acc[g].n_flagged += e1 - e0;
+        acc[g].n_bad += nb;
+        acc[g].n_residual += nr;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // variance gradient: grad[S_l] += w^2 t_l, w2sum += w^2
 
-__global__ void __launch_bounds__(64) k_vargrad(const uint8_t* __restrict__ img, uint32_t graph, uint2 key,
+__global__ void __launch_bounds__(64) k_vargrad(const uint8_t* __restrict__ img_, uint32_t graph, uint2 key,
                                                 uint64_t first, uint64_t count, double* grad, double* w2sum) {
+    const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     extern __shared__ char lds[];
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const DevGraph& G = dev_graph(img, graph);
+    const QA_RO DevGraph& G = dev_graph(img, graph);
     LV<double> vars, polys;
     lane_views<double>(lds, G.npoly, vars, polys);
     // z after the polynomial region
     double* zb = reinterpret_cast<double*>(lds + lds_bytes_dev<double>(G.npoly, blockDim.x));
     double w2 = 0.0;
     if (i < count) {
-        const double* D = reinterpret_cast<const double*>(img + G.deg_off);
-        const double* W = reinterpret_cast<const double*>(img + G.w_off);
+        const QA_RO double* D = reinterpret_cast<const QA_RO double*>(img + G.deg_off);
+        const QA_RO double* W = reinterpret_cast<const QA_RO double*>(img + G.w_off);
         Stream st{key, graph, first + i};
         uint8_t order[QA_MAXM];
         double tl[QA_MAXM], lp, cond;
@@ -785,13 +871,13 @@ extern "C" int qa_accumulate(const double* f, const double* logp, uint64_t count
 
 // work buffer layout for qa_integrate
 struct WorkLayout {
-    size_t counter, gtile0, budget, partial, nflag, flags, scale, nsel, seloff, sel, zbuf, total;
+    size_t counter, gtile0, budget, partial, nflag, flags, scale, nsel, seloff, sel, fpart, fcond, zbuf, total;
 };
 static WorkLayout work_layout(size_t ng, uint32_t tile, uint32_t per_round, uint32_t grid) {
     WorkLayout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = (o + bytes + 255) / 256 * 256; return r; };
-    L.counter = take(16);
+    L.counter = take(64);
     L.gtile0 = take(8 * (ng + 1));
     L.budget = take(8 * ng);
     L.partial = take(sizeof(Partial) * per_round);
@@ -801,12 +887,28 @@ static WorkLayout work_layout(size_t ng, uint32_t tile, uint32_t per_round, uint
     L.nsel = take(4 * per_round);
     L.seloff = take(4 * per_round);
     L.sel = take(4 * (size_t)per_round * tile);
+    // partial results: at most max(64 * grid, entries) (slices only when chunks < waves)
+    const size_t nfp = std::max<size_t>((size_t)per_round * tile, 64 * (size_t)grid);
+    L.fpart = take(sizeof(DD) * nfp);
+    L.fcond = take(8 * (size_t)per_round * tile);
     L.zbuf = take(8ull * QA_MAXM * 64 * grid);
     L.total = o;
     return L;
 }
 
-static const uint32_t kPerRound = 2048;
+// a round holds at most this many samples (flag storage: 68 B per sample)
+static const uint64_t kRoundSamples = 1ull << 25;
+static const uint32_t kDefaultTile = 256;
+
+static uint32_t tiles_per_round(uint64_t ntiles, uint32_t tile) {
+    const uint64_t cap = std::max<uint64_t>(1, kRoundSamples / tile);
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ntiles, cap));
+}
+static uint64_t count_tiles(const uint64_t* budgets, size_t ng, uint32_t tile) {
+    uint64_t t = 0;
+    for (size_t g = 0; g < ng; ++g) t += (budgets[g] + tile - 1) / tile;
+    return t;
+}
 
 static uint32_t default_grid() {
     int dev = 0, ncu = 256;
@@ -818,12 +920,12 @@ static uint32_t default_grid() {
 }
 
 extern "C" int qa_work_bytes(const qa_set* s, const uint64_t* budgets, uint32_t tile, size_t* bytes) {
-    if (!s || !bytes) return qa_fail(QA_EINVAL, "NULL argument");
-    (void)budgets;
-    if (tile == 0) tile = 1024;
+    if (!s || !bytes || !budgets) return qa_fail(QA_EINVAL, "NULL argument");
+    if (tile == 0) tile = kDefaultTile;
     if (tile % 64) return qa_fail(QA_EINVAL, "tile must be a multiple of 64");
+    const size_t ng = qa_set_size(s);
     // enough persistent waves for any grid up to 8 per CU on 256 CUs
-    *bytes = work_layout(qa_set_size(s), tile, kPerRound, 2048).total;
+    *bytes = work_layout(ng, tile, tiles_per_round(count_tiles(budgets, ng, tile), tile), 2048).total;
     return QA_OK;
 }
 
@@ -835,19 +937,20 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     if (!s || !budgets || !work || !acc) return qa_fail(QA_EINVAL, "NULL argument");
     const size_t ng = qa_set_size(s);
     if (reinterpret_cast<const DevHeader*>(img->data())->ngraphs != ng) return qa_fail(QA_EINVAL, "set / image mismatch");
-    if (tile == 0) tile = 1024;
+    if (tile == 0) tile = kDefaultTile;
     if (tile % 64) return qa_fail(QA_EINVAL, "tile must be a multiple of 64");
     if (grid == 0) grid = default_grid();
     if (grid > 2048) return qa_fail(QA_EINVAL, "grid too large (max 2048 waves)");
-    WorkLayout L = work_layout(ng, tile, kPerRound, grid);
-    if (work_bytes < L.total) return qa_fail(QA_ECAP, "work buffer too small");
     std::vector<uint64_t> g0(ng + 1, 0);
     for (size_t g = 0; g < ng; ++g) g0[g + 1] = g0[g] + (budgets[g] + tile - 1) / tile;
     const uint64_t ntiles = g0[ng];
+    const uint32_t per_round = tiles_per_round(ntiles, tile);
+    WorkLayout L = work_layout(ng, tile, per_round, grid);
+    if (work_bytes < L.total) return qa_fail(QA_ECAP, "work buffer too small");
     hipStream_t st = (hipStream_t)stream;
     char* wb = (char*)work;
-    uint32_t zero[4] = {0, 0, 0, 0};
-    HIPCHK(hipMemcpyAsync(wb + L.counter, zero, 16, hipMemcpyHostToDevice, st));
+    uint32_t zero[16] = {};
+    HIPCHK(hipMemcpyAsync(wb + L.counter, zero, sizeof zero, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(wb + L.gtile0, g0.data(), 8 * (ng + 1), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(wb + L.budget, budgets, 8 * ng, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(acc, 0, sizeof(qa_acc) * ng, st));
@@ -864,9 +967,12 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     w.nsel = (uint32_t*)(wb + L.nsel);
     w.seloff = (uint32_t*)(wb + L.seloff);
     w.sel = (uint32_t*)(wb + L.sel);
+    w.fpart = (DD*)(wb + L.fpart);
+    w.fcond = (double*)(wb + L.fcond);
+    w.grid = grid;
     w.zbuf = (double*)(wb + L.zbuf);
     w.tile = tile;
-    w.per_round = kPerRound;
+    w.per_round = per_round;
     w.ng = (uint32_t)ng;
     w.ntiles = ntiles;
     w.first = first;
@@ -874,7 +980,7 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     int maxpoly = 1;
     for (size_t g = 0; g < ng; ++g) maxpoly = std::max(maxpoly, host_graph(*img, (uint32_t)g)->npoly);
     const size_t lds_fp = lds_bytes<ER>(maxpoly, 64), lds_dd = lds_bytes<DD>(maxpoly, 64);
-    const uint64_t rounds = (ntiles + kPerRound - 1) / kPerRound;
+    const uint64_t rounds = (ntiles + per_round - 1) / per_round;
     if (int rc = lds_attr(k_fused, lds_fp)) return rc;
     if (int rc = lds_attr(k_fix_dd, lds_dd)) return rc;
     // one round = two graphs captured on a private stream (capture is not allowed
@@ -901,12 +1007,13 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     }
     if (ce == hipSuccess) ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (ce == hipSuccess) {
-        const dim3 gng((unsigned)((ng + 63) / 64));
+        const dim3 gng((unsigned)ng);
         hipLaunchKernelGGL(k_scale, gng, dim3(64), 0, cs, w, acc);
         hipLaunchKernelGGL(k_select, dim3(grid), dim3(64), 0, cs, w);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, cs, w);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, cs, w);
         hipLaunchKernelGGL(k_compact, dim3(grid), dim3(64), 0, cs, w);
         hipLaunchKernelGGL(k_fix_dd, dim3(grid), dim3(64), lds_dd, cs, (const uint8_t*)dev, key, w);
+        hipLaunchKernelGGL(k_fix_combine, dim3(512), dim3(256), 0, cs, w);
         hipLaunchKernelGGL(k_reduce, gng, dim3(64), 0, cs, w, acc);
         hipLaunchKernelGGL(k_next_round, dim3(1), dim3(64), 0, cs, w);
         ce = hipStreamEndCapture(cs, &gb);

@@ -13,6 +13,15 @@
 #define QA_VAR_C 65
 #define QA_MAXPOLY 16      // live piece-result polynomials per term
 
+// The device image is read-only for every kernel: device code reads it
+// through the constant address space, so that wave-uniform reads become
+// scalar loads even in kernels that also store to global memory.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define QA_RO __attribute__((address_space(4)))
+#else
+#define QA_RO
+#endif
+
 enum { QA_OP_A = 0, QA_OP_LMU = 1, QA_OP_L = 2, QA_OP_UV = 3, QA_OP_US = 4 };
 
 struct DevHeader {
