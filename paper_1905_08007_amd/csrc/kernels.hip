@@ -365,6 +365,7 @@ struct Work {
     double* fcond;           // double-double pass: geometry conditioning per selected entry
     uint32_t grid;           // persistent waves of the double-double pass
     double* zbuf;            // per persistent wave: QA_MAXM * 64
+    ER* pbuf;                // per persistent wave of the fused pass: piece results [QA_MAXPOLY * QA_MAXN][64]
     uint32_t tile, per_round, ng;
     uint64_t ntiles;
     uint64_t first;
@@ -411,33 +412,42 @@ __global__ void k_next_round(Work w) {
 
 // Fused pass: sample, evaluate in FP64 with the ER estimate, accumulate w and
 // w^2 per tile, and list the points whose estimate exceeds 1e-11 |f|
-// (candidates for the double-double pass).
-__global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img_, uint2 key, Work w) {
+// (candidates for the double-double pass).  A workgroup of kFusedWaves waves
+// (one per SIMD of a CU) takes a tile at a time, so that its waves walk the
+// same coefficient tables together and share the CU's scalar cache.  LDS
+// holds only the geometry variables (75 doubles per lane); the piece results
+// live in a per-wave global buffer.
+constexpr int kFusedWaves = 4;
+constexpr int kFusedThreads = 64 * kFusedWaves;
+__global__ void __launch_bounds__(kFusedThreads) k_fused(const uint8_t* __restrict__ img_, uint2 key, Work w) {
     const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     extern __shared__ char lds[];
-    const int lane = threadIdx.x;
-    LV<double> vars;
-    LV<ER> polys;
-    lane_views<ER>(lds, 0, vars, polys);
-    double* zb = w.zbuf + (uint64_t)blockIdx.x * QA_MAXM * 64;
+    __shared__ uint32_t sh_t, sh_cnt[kFusedWaves];
+    __shared__ double sh_s[kFusedWaves][5];
+    __shared__ uint64_t sh_n[kFusedWaves][2];
+    const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+    LV<double> vars{reinterpret_cast<double*>(lds) + tid, kFusedThreads};
+    const uint64_t gw = (uint64_t)blockIdx.x * kFusedWaves + wv;
+    LV<ER> polys{w.pbuf + gw * (QA_MAXPOLY * QA_MAXN * 64) + lane, 64};
+    double* zb = w.zbuf + gw * QA_MAXM * 64;
     uint64_t rt0;
     const uint32_t nr = round_len(w, rt0);
     // The round's tiles (graph-major) are split into kQueues contiguous ranges.
-    // Workgroups are dispatched to the XCDs round-robin, so the waves of one
-    // XCD share a range, and with it the coefficient tables in their L2; a
-    // wave whose range is drained helps the following ones.
+    // Workgroups are dispatched to the XCDs round-robin, so the workgroups of
+    // one XCD share a range, and with it the coefficient tables in their L2; a
+    // workgroup whose range is drained helps the following ones.
     const uint32_t x0 = blockIdx.x % kQueues;
     for (uint32_t k = 0; k < kQueues; ++k) {
       const uint32_t x = (x0 + k) % kQueues;
       const uint32_t qlo = (uint32_t)((uint64_t)nr * x / kQueues), qhi = (uint32_t)((uint64_t)nr * (x + 1) / kQueues);
       for (;;) {
-        uint32_t t = 0;
-        if (lane == 0) t = atomicAdd(w.counter + x, 1u);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));   // wave-uniform: scalar registers, scalar loads
+        if (tid == 0) sh_t = atomicAdd(w.counter + x, 1u);
+        __syncthreads();
+        uint32_t t = __builtin_amdgcn_readfirstlane(sh_t);   // workgroup-uniform: scalar loads
+        __syncthreads();
         if (t >= qhi - qlo) break;
         t += qlo;
         const uint64_t gt = rt0 + t;
-        Partial pr{};
         uint32_t g, cnt;
         uint64_t s0;
         tile_of(w, gt, g, s0, cnt);
@@ -448,10 +458,10 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img_, 
         double s2g = 0.0;
         uint64_t n = 0, bad = 0;
         uint32_t nfl = 0;
-        for (uint32_t base = 0; base < cnt; base += 64) {
-            const uint32_t j = base + lane;
+        for (uint32_t base = 0; base < cnt; base += kFusedThreads) {
+            const uint32_t j = base + tid;
             const bool act = j < cnt;
-            double wv = 0.0, ew = 0.0, qv = 0.0, cnd = 1.0, ipv = 0.0;
+            double wv_ = 0.0, ew = 0.0, qv = 0.0, cnd = 1.0, ipv = 0.0;
             bool flagged = false, good = false;
             if (act) {
                 Stream st{key, g, s0 + j};
@@ -467,27 +477,35 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img_, 
                     const double ip = exp(-lp);
                     qv = r.q;
                     cnd = cond;
-                    wv = r.v * ip;
+                    wv_ = r.v * ip;
                     ew = e * ip;
                     ipv = ip;
-                    good = isfinite(wv);
+                    good = isfinite(wv_);
                     flagged = good && !(e <= 1e-11 * fabs(r.v));
                 }
             }
             if (act && good) {
-                s1 = s1 + dd(wv);
-                s2 = s2 + two_prod(wv, wv);
-                if (!flagged) s2g += wv * wv;
+                s1 = s1 + dd(wv_);
+                s2 = s2 + two_prod(wv_, wv_);
+                if (!flagged) s2g += wv_ * wv_;
                 ++n;
             } else if (act) {
                 ++bad;
             }
+            // candidate list: positions in wave order, then lane order
             const uint64_t mask = __ballot(flagged);
+            if (lane == 0) sh_cnt[wv] = (uint32_t)__popcll(mask);
+            __syncthreads();
+            uint32_t off = nfl, tot = 0;
+            for (int v = 0; v < kFusedWaves; ++v) {
+                if (v < wv) off += sh_cnt[v];
+                tot += sh_cnt[v];
+            }
             if (flagged) {
-                const uint32_t pos = nfl + __popcll(mask & ((1ull << lane) - 1));
+                const uint32_t pos = off + __popcll(mask & ((1ull << lane) - 1));
                 FlagEntry& fe = w.flags[(uint64_t)t * w.tile + pos];
                 fe.sample = s0 + j;
-                fe.w = wv;
+                fe.w = wv_;
                 fe.estw = ew;
                 fe.q = qv;
                 fe.cond = cnd;
@@ -498,7 +516,8 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img_, 
                 fe.fixed = 0;
                 fe.residual = 0;
             }
-            nfl += __popcll(mask);
+            nfl += tot;
+            __syncthreads();
         }
         s1 = wave_sum_dd(s1);
         s2 = wave_sum_dd(s2);
@@ -506,12 +525,30 @@ __global__ void __launch_bounds__(64) k_fused(const uint8_t* __restrict__ img_, 
         n = wave_sum_u64(n);
         bad = wave_sum_u64(bad);
         if (lane == 0) {
-            pr.s1_hi = s1.hi; pr.s1_lo = s1.lo; pr.s2_hi = s2.hi; pr.s2_lo = s2.lo;
-            pr.s2g = s2g;
-            pr.n = n; pr.nflag = nfl; pr.nbad = bad;
+            sh_s[wv][0] = s1.hi; sh_s[wv][1] = s1.lo; sh_s[wv][2] = s2.hi; sh_s[wv][3] = s2.lo; sh_s[wv][4] = s2g;
+            sh_n[wv][0] = n; sh_n[wv][1] = bad;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            // waves combined in a fixed order
+            DD a1{0, 0}, a2{0, 0};
+            double ag = 0.0;
+            uint64_t an = 0, ab = 0;
+            for (int v = 0; v < kFusedWaves; ++v) {
+                a1 = a1 + DD{sh_s[v][0], sh_s[v][1]};
+                a2 = a2 + DD{sh_s[v][2], sh_s[v][3]};
+                ag += sh_s[v][4];
+                an += sh_n[v][0];
+                ab += sh_n[v][1];
+            }
+            Partial pr{};
+            pr.s1_hi = a1.hi; pr.s1_lo = a1.lo; pr.s2_hi = a2.hi; pr.s2_lo = a2.lo;
+            pr.s2g = ag;
+            pr.n = an; pr.nflag = nfl; pr.nbad = ab;
             w.partial[t] = pr;
             w.nflag[t] = nfl;
         }
+        __syncthreads();
       }
     }
 }
@@ -871,7 +908,7 @@ extern "C" int qa_accumulate(const double* f, const double* logp, uint64_t count
 
 // work buffer layout for qa_integrate
 struct WorkLayout {
-    size_t counter, gtile0, budget, partial, nflag, flags, scale, nsel, seloff, sel, fpart, fcond, zbuf, total;
+    size_t counter, gtile0, budget, partial, nflag, flags, scale, nsel, seloff, sel, fpart, fcond, zbuf, pbuf, total;
 };
 static WorkLayout work_layout(size_t ng, uint32_t tile, uint32_t per_round, uint32_t grid) {
     WorkLayout L{};
@@ -892,6 +929,7 @@ static WorkLayout work_layout(size_t ng, uint32_t tile, uint32_t per_round, uint
     L.fpart = take(sizeof(DD) * nfp);
     L.fcond = take(8 * (size_t)per_round * tile);
     L.zbuf = take(8ull * QA_MAXM * 64 * grid);
+    L.pbuf = take(sizeof(ER) * QA_MAXPOLY * QA_MAXN * 64 * (size_t)grid);
     L.total = o;
     return L;
 }
@@ -941,6 +979,7 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     if (tile % 64) return qa_fail(QA_EINVAL, "tile must be a multiple of 64");
     if (grid == 0) grid = default_grid();
     if (grid > 2048) return qa_fail(QA_EINVAL, "grid too large (max 2048 waves)");
+    grid = (grid + kFusedWaves - 1) / kFusedWaves * kFusedWaves;   // the fused pass runs workgroups of 4 waves
     std::vector<uint64_t> g0(ng + 1, 0);
     for (size_t g = 0; g < ng; ++g) g0[g + 1] = g0[g] + (budgets[g] + tile - 1) / tile;
     const uint64_t ntiles = g0[ng];
@@ -971,6 +1010,7 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     w.fcond = (double*)(wb + L.fcond);
     w.grid = grid;
     w.zbuf = (double*)(wb + L.zbuf);
+    w.pbuf = (ER*)(wb + L.pbuf);
     w.tile = tile;
     w.per_round = per_round;
     w.ng = (uint32_t)ng;
@@ -979,7 +1019,7 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     const uint2 key = make_uint2((uint32_t)seed, tag);
     int maxpoly = 1;
     for (size_t g = 0; g < ng; ++g) maxpoly = std::max(maxpoly, host_graph(*img, (uint32_t)g)->npoly);
-    const size_t lds_fp = lds_bytes<ER>(maxpoly, 64), lds_dd = lds_bytes<DD>(maxpoly, 64);
+    const size_t lds_fp = sizeof(double) * QA_NVAR * kFusedThreads, lds_dd = lds_bytes<DD>(maxpoly, 64);
     const uint64_t rounds = (ntiles + per_round - 1) / per_round;
     if (int rc = lds_attr(k_fused, lds_fp)) return rc;
     if (int rc = lds_attr(k_fix_dd, lds_dd)) return rc;
@@ -1002,7 +1042,8 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (ce == hipSuccess) {
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, cs, w);
-        hipLaunchKernelGGL(k_fused, dim3(grid), dim3(64), lds_fp, cs, (const uint8_t*)dev, key, w);
+        hipLaunchKernelGGL(k_fused, dim3(grid / kFusedWaves), dim3(kFusedThreads), lds_fp, cs, (const uint8_t*)dev,
+                           key, w);
         ce = hipStreamEndCapture(cs, &ga);
     }
     if (ce == hipSuccess) ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
