@@ -3,6 +3,7 @@
 #pragma once
 #include "numeric.h"
 #include "qa_dev.h"
+#include <stddef.h>
 #include <type_traits>
 
 // lane view of per-lane scratch laid out [element][lane]
@@ -209,6 +210,39 @@ QA_HD void geometry(const QA_RO DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, 
 }
 
 // ---------------------------------------------------------------------------
+// A block header held in scalar registers: the 40-byte record is read as ten
+// wave-uniform words and its byte fields are extracted with scalar shifts
+// (a per-lane byte load would stall each block on vector-memory latency).
+QA_HD uint32_t uni(uint32_t x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_readfirstlane(x);
+#else
+    return x;
+#endif
+}
+struct BH {
+    uint32_t w[10];
+    QA_HD int byte(int o) const { return (int)((w[o >> 2] >> (8 * (o & 3))) & 0xffu); }
+    QA_HD int k() const { return byte(0); }
+    QA_HD int r() const { return byte(1); }
+    QA_HD int cexp() const { return byte(2); }
+    QA_HD uint32_t coef() const { return w[1]; }
+    QA_HD int bidx(int q) const { return byte(8 + q); }
+    QA_HD int aidx(int i) const { return byte(13 + i); }
+    QA_HD int cidx(int i) const { return byte(25 + i); }
+};
+static_assert(sizeof(DevBlock) == 40 && offsetof(DevBlock, coef) == 4 && offsetof(DevBlock, bidx) == 8 &&
+                  offsetof(DevBlock, aidx) == 13 && offsetof(DevBlock, cidx) == 25,
+              "block header layout");
+QA_HD BH load_bh(const QA_RO DevBlock& b) {
+    const QA_RO uint32_t* p = reinterpret_cast<const QA_RO uint32_t*>(&b);
+    BH h;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) h.w[i] = uni(p[i]);
+    return h;
+}
+
+// ---------------------------------------------------------------------------
 // multilinear fold: sum_s c[s] prod_{bit i of s} A[map(i)], r <= QA_MAXR, where
 // map skips the compile-time index J (J = QA_MAXR: no skip).  Used with the
 // free-slot values A of a block; the q-derivative part folds the other slots.
@@ -254,28 +288,28 @@ template <class T, int J, bool Abs = false> QA_HD T fold(const QA_RO double* c, 
 
 // sum over the free slot j carrying the q-derivative: C_j * fold(others)
 template <class T, class S, int J> struct QTerms {
-    QA_HD static void run(T& s, const QA_RO double* c, const T* A, int r, LV<S> vars, const QA_RO DevBlock& b) {
+    QA_HD static void run(T& s, const QA_RO double* c, const T* A, int r, LV<S> vars, const BH& b) {
         if (J >= r) return;
         const int half = 1 << (r - 1);
-        s = s + lift_to<T>(vars[b.cidx[J]]) * fold<T, J>(c + (1 << r) + J * half, A, r - 1);
+        s = s + lift_to<T>(vars[b.cidx(J)]) * fold<T, J>(c + (1 << r) + J * half, A, r - 1);
         QTerms<T, S, J + 1>::run(s, c, A, r, vars, b);
     }
 };
 template <class T, class S> struct QTerms<T, S, QA_MAXR> {
-    QA_HD static void run(T&, const QA_RO double*, const T*, int, LV<S>, const QA_RO DevBlock&) {}
+    QA_HD static void run(T&, const QA_RO double*, const T*, int, LV<S>, const BH&) {}
 };
 
 // one block: w * (Gamma_0 fold + Gamma_1 folds)
 template <class T, class S>
-QA_HD T eval_block(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars, bool has_q) {
-    const int k = b.k, r = b.r;
+QA_HD T eval_block(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
+    const int k = b.k(), r = b.r();
     T w = from_d<T>(1.0);
 #pragma unroll
     for (int q = 0; q < QA_MAXK; ++q)
-        if (q < k) w = w * lift_to<T>(vars[b.bidx[q]]);
+        if (q < k) w = w * lift_to<T>(vars[b.bidx(q)]);
     T A[QA_MAXR + 1];
 #pragma unroll
-    for (int i = 0; i < QA_MAXR; ++i) A[i] = i < r ? lift_to<T>(vars[b.aidx[i]]) : from_d<T>(0.0);
+    for (int i = 0; i < QA_MAXR; ++i) A[i] = i < r ? lift_to<T>(vars[b.aidx(i)]) : from_d<T>(0.0);
     A[QA_MAXR] = from_d<T>(0.0);
     T s = fold<T, QA_MAXR>(c, A, r);
     if (has_q) QTerms<T, S, 0>::run(s, c, A, r, vars, b);
@@ -285,25 +319,25 @@ QA_HD T eval_block(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars, b
 // statically sized block (R free slots, R <= QA_STATIC_R): fully unrolled folds
 #define QA_STATIC_R 6
 template <class T, class S, int R, int J> struct QStatic {
-    QA_HD static void run(T& s, const QA_RO double* c, const T* A, LV<S> vars, const QA_RO DevBlock& b) {
-        s = s + lift_to<T>(vars[b.cidx[J]]) * Fold<T, R - 1, J>::run(c + (1 << R) + J * (1 << (R - 1)), A);
+    QA_HD static void run(T& s, const QA_RO double* c, const T* A, LV<S> vars, const BH& b) {
+        s = s + lift_to<T>(vars[b.cidx(J)]) * Fold<T, R - 1, J>::run(c + (1 << R) + J * (1 << (R - 1)), A);
         QStatic<T, S, R, J + 1>::run(s, c, A, vars, b);
     }
 };
 template <class T, class S, int R> struct QStatic<T, S, R, R> {
-    QA_HD static void run(T&, const QA_RO double*, const T*, LV<S>, const QA_RO DevBlock&) {}
+    QA_HD static void run(T&, const QA_RO double*, const T*, LV<S>, const BH&) {}
 };
 
 template <class T, class S, int R>
-QA_HD T block_static(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars, bool has_q) {
-    const int k = b.k;
+QA_HD T block_static(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
+    const int k = b.k();
     T w = from_d<T>(1.0);
 #pragma unroll
     for (int q = 0; q < QA_MAXK; ++q)
-        if (q < k) w = w * lift_to<T>(vars[b.bidx[q]]);
+        if (q < k) w = w * lift_to<T>(vars[b.bidx(q)]);
     T A[R + 1];
 #pragma unroll
-    for (int i = 0; i < R; ++i) A[i] = lift_to<T>(vars[b.aidx[i]]);
+    for (int i = 0; i < R; ++i) A[i] = lift_to<T>(vars[b.aidx(i)]);
     A[R] = from_d<T>(0.0);
     T s = Fold<T, R, QA_MAXR>::run(c, A);
     if (has_q) QStatic<T, S, R, 0>::run(s, c, A, vars, b);
@@ -313,46 +347,46 @@ QA_HD T block_static(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars,
 // sum over the free slot j carrying the q-derivative, value and square folds
 template <class S, int J> struct QTermsQ {
     QA_HD static void run(double& s, double& sq, const QA_RO double* c, const double* A, const double* A2, int r, LV<S> vars,
-                          const QA_RO DevBlock& b) {
+                          const BH& b) {
         if (J >= r) return;
         const QA_RO double* cc = c + (1 << r) + J * (1 << (r - 1));
-        const double cj = vars[b.cidx[J]];
+        const double cj = vars[b.cidx(J)];
         s = s + cj * fold<double, J>(cc, A, r - 1);
         sq = sq + (cj * cj) * fold<double, J, true>(cc, A2, r - 1);
         QTermsQ<S, J + 1>::run(s, sq, c, A, A2, r, vars, b);
     }
 };
 template <class S> struct QTermsQ<S, QA_MAXR> {
-    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, int, LV<S>, const QA_RO DevBlock&) {}
+    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, int, LV<S>, const BH&) {}
 };
 
 // Block in EQ: the value, and q = 2^cexp * w^2 * sum_s |c_s| m_s^2 >= the sum
 // of squares of the block's monomials (m_s: product of the slot values of s;
 // 2^cexp >= max |c|).  Both folds share the coefficient loads.
 template <class S>
-QA_HD EQ eval_block_q(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars, bool has_q) {
-    const int k = b.k, r = b.r;
+QA_HD EQ eval_block_q(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
+    const int k = b.k(), r = b.r();
     double w = 1.0;
 #pragma unroll
     for (int q = 0; q < QA_MAXK; ++q)
-        if (q < k) w = w * vars[b.bidx[q]];
+        if (q < k) w = w * vars[b.bidx(q)];
     double A[QA_MAXR + 1], A2[QA_MAXR + 1];
 #pragma unroll
     for (int i = 0; i < QA_MAXR; ++i) {
-        A[i] = i < r ? vars[b.aidx[i]] : 0.0;
+        A[i] = i < r ? vars[b.aidx(i)] : 0.0;
         A2[i] = A[i] * A[i];
     }
     A[QA_MAXR] = A2[QA_MAXR] = 0.0;
     double s = fold<double, QA_MAXR>(c, A, r);
     double sq = fold<double, QA_MAXR, true>(c, A2, r);
     if (has_q) QTermsQ<S, 0>::run(s, sq, c, A, A2, r, vars, b);
-    return EQ{w * s, ldexp(w * w * sq, b.cexp)};
+    return EQ{w * s, ldexp(w * w * sq, b.cexp())};
 }
 
 template <class S, int R, int J> struct QStaticQ {
     QA_HD static void run(double& s, double& sq, const QA_RO double* c, const double* A, const double* A2, LV<S> vars,
-                          const QA_RO DevBlock& b) {
-        const double cj = vars[b.cidx[J]];
+                          const BH& b) {
+        const double cj = vars[b.cidx(J)];
         const QA_RO double* cc = c + (1 << R) + J * (1 << (R - 1));
         s = s + cj * Fold<double, R - 1, J>::run(cc, A);
         sq = sq + (cj * cj) * Fold<double, R - 1, J, true>::run(cc, A2);
@@ -360,30 +394,30 @@ template <class S, int R, int J> struct QStaticQ {
     }
 };
 template <class S, int R> struct QStaticQ<S, R, R> {
-    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, LV<S>, const QA_RO DevBlock&) {}
+    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, LV<S>, const BH&) {}
 };
 
 template <class S, int R>
-QA_HD EQ block_static_q(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars, bool has_q) {
-    const int k = b.k;
+QA_HD EQ block_static_q(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
+    const int k = b.k();
     double w = 1.0;
 #pragma unroll
     for (int q = 0; q < QA_MAXK; ++q)
-        if (q < k) w = w * vars[b.bidx[q]];
+        if (q < k) w = w * vars[b.bidx(q)];
     double A[R + 1], A2[R + 1];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        A[i] = vars[b.aidx[i]];
+        A[i] = vars[b.aidx(i)];
         A2[i] = A[i] * A[i];
     }
     A[R] = A2[R] = 0.0;
     double s = Fold<double, R, QA_MAXR>::run(c, A);
     double sq = Fold<double, R, QA_MAXR, true>::run(c, A2);
     if (has_q) QStaticQ<S, R, 0>::run(s, sq, c, A, A2, vars, b);
-    return EQ{w * s, ldexp(w * w * sq, b.cexp)};
+    return EQ{w * s, ldexp(w * w * sq, b.cexp())};
 }
 template <class T, class S, int R>
-QA_HD T block_any(const QA_RO DevBlock& b, const QA_RO double* c, LV<S> vars, bool has_q) {
+QA_HD T block_any(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
     if constexpr (std::is_same<T, EQ>::value) return block_static_q<S, R>(b, c, vars, has_q);
     else return block_static<T, S, R>(b, c, vars, has_q);
 }
@@ -396,14 +430,17 @@ template <class T, class S, int R, class AT>
 QA_HD void group_static(const QA_RO DevBlock* blocks, int b0, int b1, const QA_RO double* coefs, LV<S> vars, bool hq, AT& acc) {
     int bi = b0;
     for (; bi + 1 < b1; bi += 2) {
-        const QA_RO DevBlock& x = blocks[bi];
-        const QA_RO DevBlock& y = blocks[bi + 1];
-        const T vx = block_any<T, S, R>(x, coefs + x.coef, vars, hq);
-        const T vy = block_any<T, S, R>(y, coefs + y.coef, vars, hq);
-        acc_add(acc, vx, 2 * (x.k + R) + 3);
-        acc_add(acc, vy, 2 * (y.k + R) + 3);
+        const BH x = load_bh(blocks[bi]);
+        const BH y = load_bh(blocks[bi + 1]);
+        const T vx = block_any<T, S, R>(x, coefs + x.coef(), vars, hq);
+        const T vy = block_any<T, S, R>(y, coefs + y.coef(), vars, hq);
+        acc_add(acc, vx, 2 * (x.k() + R) + 3);
+        acc_add(acc, vy, 2 * (y.k() + R) + 3);
     }
-    if (bi < b1) acc_add(acc, block_any<T, S, R>(blocks[bi], coefs + blocks[bi].coef, vars, hq), 2 * (blocks[bi].k + R) + 3);
+    if (bi < b1) {
+        const BH x = load_bh(blocks[bi]);
+        acc_add(acc, block_any<T, S, R>(x, coefs + x.coef(), vars, hq), 2 * (x.k() + R) + 3);
+    }
 }
 
 // Evaluate one coefficient table: poly[k] = (1/denom) * sum over blocks with k
@@ -424,7 +461,7 @@ QA_HD void eval_table(const QA_RO uint8_t* img, const QA_RO DevTable& tb, LV<S> 
         const int b0 = k0 + (k1 - k0) * slice / nslices, b1 = k0 + (k1 - k0) * (slice + 1) / nslices;
         if (k < n && b0 < b1) {
             // the double-double path (flagged points only) uses the compact generic loop
-            const int rsel = std::is_same<T, DD>::value ? -1 : blocks[b0].r;
+            const int rsel = std::is_same<T, DD>::value ? -1 : load_bh(blocks[b0]).r();
             switch (rsel) {
                 case 0: group_static<BT, S, 0>(blocks, b0, b1, coefs, vars, hq, acc); break;
                 case 1: group_static<BT, S, 1>(blocks, b0, b1, coefs, vars, hq, acc); break;
@@ -435,11 +472,11 @@ QA_HD void eval_table(const QA_RO uint8_t* img, const QA_RO DevTable& tb, LV<S> 
                 case 6: group_static<BT, S, 6>(blocks, b0, b1, coefs, vars, hq, acc); break;
                 default:
                     for (int bi = b0; bi < b1; ++bi) {
-                        const QA_RO DevBlock& b = blocks[bi];
+                        const BH b = load_bh(blocks[bi]);
                         if constexpr (std::is_same<BT, EQ>::value)
-                            acc_add(acc, eval_block_q<S>(b, coefs + b.coef, vars, hq), 2 * (b.k + b.r) + 3);
+                            acc_add(acc, eval_block_q<S>(b, coefs + b.coef(), vars, hq), 2 * (b.k() + b.r()) + 3);
                         else
-                            acc_add(acc, eval_block<BT, S>(b, coefs + b.coef, vars, hq), 2 * (b.k + b.r) + 3);
+                            acc_add(acc, eval_block<BT, S>(b, coefs + b.coef(), vars, hq), 2 * (b.k() + b.r()) + 3);
                     }
             }
         }
