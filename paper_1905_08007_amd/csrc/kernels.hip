@@ -366,6 +366,7 @@ struct Work {
     uint32_t grid;           // persistent waves of the double-double pass
     double* zbuf;            // per persistent wave: QA_MAXM * 64
     ER* pbuf;                // per persistent wave of the fused pass: piece results [QA_MAXPOLY * QA_MAXN][64]
+    double* vbuf;            // per persistent wave of the fused pass: geometry variables [QA_NVAR][64]
     uint32_t tile, per_round, ng;
     uint64_t ntiles;
     uint64_t first;
@@ -419,15 +420,16 @@ __global__ void k_next_round(Work w) {
 // live in a per-wave global buffer.
 constexpr int kFusedWaves = 4;
 constexpr int kFusedThreads = 64 * kFusedWaves;
-__global__ void __launch_bounds__(kFusedThreads) k_fused(const uint8_t* __restrict__ img_, uint2 key, Work w) {
+__global__ void __launch_bounds__(kFusedThreads, 2) k_fused(const uint8_t* __restrict__ img_, uint2 key, Work w) {
     const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     extern __shared__ char lds[];
     __shared__ uint32_t sh_t, sh_cnt[kFusedWaves];
     __shared__ double sh_s[kFusedWaves][5];
     __shared__ uint64_t sh_n[kFusedWaves][2];
     const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
-    LV<double> vars{reinterpret_cast<double*>(lds) + tid, kFusedThreads};
     const uint64_t gw = (uint64_t)blockIdx.x * kFusedWaves + wv;
+    LV<double> vars{w.vbuf + gw * (QA_NVAR * 64) + lane, 64};
+    (void)lds;
     LV<ER> polys{w.pbuf + gw * (QA_MAXPOLY * QA_MAXN * 64) + lane, 64};
     double* zb = w.zbuf + gw * QA_MAXM * 64;
     uint64_t rt0;
@@ -908,7 +910,7 @@ extern "C" int qa_accumulate(const double* f, const double* logp, uint64_t count
 
 // work buffer layout for qa_integrate
 struct WorkLayout {
-    size_t counter, gtile0, budget, partial, nflag, flags, scale, nsel, seloff, sel, fpart, fcond, zbuf, pbuf, total;
+    size_t counter, gtile0, budget, partial, nflag, flags, scale, nsel, seloff, sel, fpart, fcond, zbuf, pbuf, vbuf, total;
 };
 static WorkLayout work_layout(size_t ng, uint32_t tile, uint32_t per_round, uint32_t grid) {
     WorkLayout L{};
@@ -930,6 +932,7 @@ static WorkLayout work_layout(size_t ng, uint32_t tile, uint32_t per_round, uint
     L.fcond = take(8 * (size_t)per_round * tile);
     L.zbuf = take(8ull * QA_MAXM * 64 * grid);
     L.pbuf = take(sizeof(ER) * QA_MAXPOLY * QA_MAXN * 64 * (size_t)grid);
+    L.vbuf = take(sizeof(double) * QA_NVAR * 64 * (size_t)grid);
     L.total = o;
     return L;
 }
@@ -954,7 +957,7 @@ static uint32_t default_grid() {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
     }
-    return (uint32_t)ncu * 4;
+    return (uint32_t)ncu * 8;
 }
 
 extern "C" int qa_work_bytes(const qa_set* s, const uint64_t* budgets, uint32_t tile, size_t* bytes) {
@@ -1011,6 +1014,7 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     w.grid = grid;
     w.zbuf = (double*)(wb + L.zbuf);
     w.pbuf = (ER*)(wb + L.pbuf);
+    w.vbuf = (double*)(wb + L.vbuf);
     w.tile = tile;
     w.per_round = per_round;
     w.ng = (uint32_t)ng;
@@ -1019,7 +1023,7 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     const uint2 key = make_uint2((uint32_t)seed, tag);
     int maxpoly = 1;
     for (size_t g = 0; g < ng; ++g) maxpoly = std::max(maxpoly, host_graph(*img, (uint32_t)g)->npoly);
-    const size_t lds_fp = sizeof(double) * QA_NVAR * kFusedThreads, lds_dd = lds_bytes<DD>(maxpoly, 64);
+    const size_t lds_fp = 0, lds_dd = lds_bytes<DD>(maxpoly, 64);
     const uint64_t rounds = (ntiles + per_round - 1) / per_round;
     if (int rc = lds_attr(k_fused, lds_fp)) return rc;
     if (int rc = lds_attr(k_fix_dd, lds_dd)) return rc;
