@@ -420,7 +420,8 @@ __global__ void k_next_round(Work w) {
 // live in a per-wave global buffer.
 constexpr int kFusedWaves = 4;
 constexpr int kFusedThreads = 64 * kFusedWaves;
-__global__ void __launch_bounds__(kFusedThreads, 2) k_fused(const uint8_t* __restrict__ img_, uint2 key, Work w) {
+constexpr int kFusedOcc = 4;   // waves per SIMD the fused pass is compiled for
+__global__ void __launch_bounds__(kFusedThreads, kFusedOcc) k_fused(const uint8_t* __restrict__ img_, uint2 key, Work w) {
     const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     extern __shared__ char lds[];
     __shared__ uint32_t sh_t, sh_cnt[kFusedWaves];
@@ -951,13 +952,15 @@ static uint64_t count_tiles(const uint64_t* budgets, size_t ng, uint32_t tile) {
     return t;
 }
 
+static const uint32_t kMaxWaves = 4096;   // persistent waves of a batched launch (16 per CU on 256 CUs)
+
 static uint32_t default_grid() {
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
     }
-    return (uint32_t)ncu * 8;
+    return (uint32_t)ncu * 4 * kFusedOcc;
 }
 
 extern "C" int qa_work_bytes(const qa_set* s, const uint64_t* budgets, uint32_t tile, size_t* bytes) {
@@ -966,7 +969,7 @@ extern "C" int qa_work_bytes(const qa_set* s, const uint64_t* budgets, uint32_t 
     if (tile % 64) return qa_fail(QA_EINVAL, "tile must be a multiple of 64");
     const size_t ng = qa_set_size(s);
     // enough persistent waves for any grid up to 8 per CU on 256 CUs
-    *bytes = work_layout(ng, tile, tiles_per_round(count_tiles(budgets, ng, tile), tile), 2048).total;
+    *bytes = work_layout(ng, tile, tiles_per_round(count_tiles(budgets, ng, tile), tile), kMaxWaves).total;
     return QA_OK;
 }
 
@@ -981,7 +984,7 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     if (tile == 0) tile = kDefaultTile;
     if (tile % 64) return qa_fail(QA_EINVAL, "tile must be a multiple of 64");
     if (grid == 0) grid = default_grid();
-    if (grid > 2048) return qa_fail(QA_EINVAL, "grid too large (max 2048 waves)");
+    if (grid > kMaxWaves) return qa_fail(QA_EINVAL, "grid too large (max 4096 waves)");
     grid = (grid + kFusedWaves - 1) / kFusedWaves * kFusedWaves;   // the fused pass runs workgroups of 4 waves
     std::vector<uint64_t> g0(ng + 1, 0);
     for (size_t g = 0; g < ng; ++g) g0[g + 1] = g0[g] + (budgets[g] + tile - 1) / tile;
