@@ -18,6 +18,20 @@ template <class T> struct CLV {
     QA_HD const T& operator[](int i) const { return p[i * stride]; }
 };
 
+// Per-lane geometry variables of the current piece in two regions, each laid
+// out [element][lane]: the contraction matrix Bbar (indices < QA_VAR_A) and the
+// flows A, C (indices QA_VAR_A ..).  The flows are read about twice as often;
+// the fused pass keeps them in LDS and Bbar in global memory.
+template <class T> struct VV {
+    T* pb;
+    int sb;
+    T* pa;
+    int sa;
+    QA_HD T& bb(int i) const { return pb[i * sb]; }
+    QA_HD T& ac(int i) const { return pa[(i - QA_VAR_A) * sa]; }
+};
+template <class T> QA_HD VV<T> vv(T* p, int stride) { return VV<T>{p, stride, p + QA_VAR_A * stride, stride}; }
+
 QA_HD int tri_idx(int a, int b) { return a <= b ? b * (b + 1) / 2 + a : a * (a + 1) / 2 + b; }
 
 // store a geometry output; in the comparing pass measure |double - dd| / (u |dd|)
@@ -53,7 +67,7 @@ template <> QA_HD void geo_scalar<DD, true>(DD& dst, const DD& x, double& cond) 
 // discrepancy in units of the double round-off, i.e. an estimate of the
 // polynomials' conditioning (the double-double error is about cond * 2^-104).
 template <class S, class T, int L, bool Cmp>
-QA_HD void geometry_L(const QA_RO DevPiece& pc, CLV<double> z, LV<S> vars, DD& Uo, DD& Vo, double& cond) {
+QA_HD void geometry_L(const QA_RO DevPiece& pc, CLV<double> z, VV<S> vars, DD& Uo, DD& Vo, double& cond) {
     T U, V;
     const int nl = pc.nlines;
     T zl[QA_MAXL];
@@ -160,8 +174,8 @@ QA_HD void geometry_L(const QA_RO DevPiece& pc, CLV<double> z, LV<S> vars, DD& U
         for (int c = 0; c < L; ++c)
             if (in[i][c]) { a = a - y[c]; cq = cq - yq[c]; }
         if (!hq) cq = from_d<T>(0.0);
-        geo_out<S, T, Cmp>(vars[QA_VAR_A + i], a, cond);
-        geo_out<S, T, Cmp>(vars[QA_VAR_C + i], cq, cond);
+        geo_out<S, T, Cmp>(vars.ac(QA_VAR_A + i), a, cond);
+        geo_out<S, T, Cmp>(vars.ac(QA_VAR_C + i), cq, cond);
         V = V + zl[i] * (from_d<T>(1.0) - a);
 #pragma unroll
         for (int d = 0; d < L; ++d) {
@@ -182,7 +196,7 @@ QA_HD void geometry_L(const QA_RO DevPiece& pc, CLV<double> z, LV<S> vars, DD& U
 #pragma unroll
                 for (int d = 0; d < L; ++d)
                     if (in[j][d]) s = s + Y[i][d];
-                geo_out<S, T, Cmp>(vars[tri_idx(i, j)], s, cond);
+                geo_out<S, T, Cmp>(vars.bb(tri_idx(i, j)), s, cond);
             }
         }
     }
@@ -192,13 +206,13 @@ QA_HD void geometry_L(const QA_RO DevPiece& pc, CLV<double> z, LV<S> vars, DD& U
 
 // plain-double pass, then the double-double pass comparing against it
 template <class S, int L>
-QA_HD void geometry_2(const QA_RO DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V, double& cond) {
+QA_HD void geometry_2(const QA_RO DevPiece& pc, CLV<double> z, VV<S> vars, DD& U, DD& V, double& cond) {
     geometry_L<S, double, L, false>(pc, z, vars, U, V, cond);
     geometry_L<S, DD, L, true>(pc, z, vars, U, V, cond);
 }
 
 template <class S>
-QA_HD void geometry(const QA_RO DevPiece& pc, CLV<double> z, LV<S> vars, DD& U, DD& V, double& cond) {
+QA_HD void geometry(const QA_RO DevPiece& pc, CLV<double> z, VV<S> vars, DD& U, DD& V, double& cond) {
     cond = 1.0;
     switch (pc.nchords) {
         case 1: geometry_2<S, 1>(pc, z, vars, U, V, cond); break;
@@ -288,28 +302,28 @@ template <class T, int J, bool Abs = false> QA_HD T fold(const QA_RO double* c, 
 
 // sum over the free slot j carrying the q-derivative: C_j * fold(others)
 template <class T, class S, int J> struct QTerms {
-    QA_HD static void run(T& s, const QA_RO double* c, const T* A, int r, LV<S> vars, const BH& b) {
+    QA_HD static void run(T& s, const QA_RO double* c, const T* A, int r, VV<S> vars, const BH& b) {
         if (J >= r) return;
         const int half = 1 << (r - 1);
-        s = s + lift_to<T>(vars[b.cidx(J)]) * fold<T, J>(c + (1 << r) + J * half, A, r - 1);
+        s = s + lift_to<T>(vars.ac(b.cidx(J))) * fold<T, J>(c + (1 << r) + J * half, A, r - 1);
         QTerms<T, S, J + 1>::run(s, c, A, r, vars, b);
     }
 };
 template <class T, class S> struct QTerms<T, S, QA_MAXR> {
-    QA_HD static void run(T&, const QA_RO double*, const T*, int, LV<S>, const BH&) {}
+    QA_HD static void run(T&, const QA_RO double*, const T*, int, VV<S>, const BH&) {}
 };
 
 // one block: w * (Gamma_0 fold + Gamma_1 folds)
 template <class T, class S>
-QA_HD T eval_block(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
+QA_HD T eval_block(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
     const int k = b.k(), r = b.r();
     T w = from_d<T>(1.0);
 #pragma unroll
     for (int q = 0; q < QA_MAXK; ++q)
-        if (q < k) w = w * lift_to<T>(vars[b.bidx(q)]);
+        if (q < k) w = w * lift_to<T>(vars.bb(b.bidx(q)));
     T A[QA_MAXR + 1];
 #pragma unroll
-    for (int i = 0; i < QA_MAXR; ++i) A[i] = i < r ? lift_to<T>(vars[b.aidx(i)]) : from_d<T>(0.0);
+    for (int i = 0; i < QA_MAXR; ++i) A[i] = i < r ? lift_to<T>(vars.ac(b.aidx(i))) : from_d<T>(0.0);
     A[QA_MAXR] = from_d<T>(0.0);
     T s = fold<T, QA_MAXR>(c, A, r);
     if (has_q) QTerms<T, S, 0>::run(s, c, A, r, vars, b);
@@ -319,25 +333,25 @@ QA_HD T eval_block(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
 // statically sized block (R free slots, R <= QA_STATIC_R): fully unrolled folds
 #define QA_STATIC_R 6
 template <class T, class S, int R, int J> struct QStatic {
-    QA_HD static void run(T& s, const QA_RO double* c, const T* A, LV<S> vars, const BH& b) {
-        s = s + lift_to<T>(vars[b.cidx(J)]) * Fold<T, R - 1, J>::run(c + (1 << R) + J * (1 << (R - 1)), A);
+    QA_HD static void run(T& s, const QA_RO double* c, const T* A, VV<S> vars, const BH& b) {
+        s = s + lift_to<T>(vars.ac(b.cidx(J))) * Fold<T, R - 1, J>::run(c + (1 << R) + J * (1 << (R - 1)), A);
         QStatic<T, S, R, J + 1>::run(s, c, A, vars, b);
     }
 };
 template <class T, class S, int R> struct QStatic<T, S, R, R> {
-    QA_HD static void run(T&, const QA_RO double*, const T*, LV<S>, const BH&) {}
+    QA_HD static void run(T&, const QA_RO double*, const T*, VV<S>, const BH&) {}
 };
 
 template <class T, class S, int R>
-QA_HD T block_static(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
+QA_HD T block_static(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
     const int k = b.k();
     T w = from_d<T>(1.0);
 #pragma unroll
     for (int q = 0; q < QA_MAXK; ++q)
-        if (q < k) w = w * lift_to<T>(vars[b.bidx(q)]);
+        if (q < k) w = w * lift_to<T>(vars.bb(b.bidx(q)));
     T A[R + 1];
 #pragma unroll
-    for (int i = 0; i < R; ++i) A[i] = lift_to<T>(vars[b.aidx(i)]);
+    for (int i = 0; i < R; ++i) A[i] = lift_to<T>(vars.ac(b.aidx(i)));
     A[R] = from_d<T>(0.0);
     T s = Fold<T, R, QA_MAXR>::run(c, A);
     if (has_q) QStatic<T, S, R, 0>::run(s, c, A, vars, b);
@@ -346,34 +360,34 @@ QA_HD T block_static(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q)
 
 // sum over the free slot j carrying the q-derivative, value and square folds
 template <class S, int J> struct QTermsQ {
-    QA_HD static void run(double& s, double& sq, const QA_RO double* c, const double* A, const double* A2, int r, LV<S> vars,
+    QA_HD static void run(double& s, double& sq, const QA_RO double* c, const double* A, const double* A2, int r, VV<S> vars,
                           const BH& b) {
         if (J >= r) return;
         const QA_RO double* cc = c + (1 << r) + J * (1 << (r - 1));
-        const double cj = vars[b.cidx(J)];
+        const double cj = vars.ac(b.cidx(J));
         s = s + cj * fold<double, J>(cc, A, r - 1);
         sq = sq + (cj * cj) * fold<double, J, true>(cc, A2, r - 1);
         QTermsQ<S, J + 1>::run(s, sq, c, A, A2, r, vars, b);
     }
 };
 template <class S> struct QTermsQ<S, QA_MAXR> {
-    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, int, LV<S>, const BH&) {}
+    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, int, VV<S>, const BH&) {}
 };
 
 // Block in EQ: the value, and q = 2^cexp * w^2 * sum_s |c_s| m_s^2 >= the sum
 // of squares of the block's monomials (m_s: product of the slot values of s;
 // 2^cexp >= max |c|).  Both folds share the coefficient loads.
 template <class S>
-QA_HD EQ eval_block_q(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
+QA_HD EQ eval_block_q(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
     const int k = b.k(), r = b.r();
     double w = 1.0;
 #pragma unroll
     for (int q = 0; q < QA_MAXK; ++q)
-        if (q < k) w = w * vars[b.bidx(q)];
+        if (q < k) w = w * vars.bb(b.bidx(q));
     double A[QA_MAXR + 1], A2[QA_MAXR + 1];
 #pragma unroll
     for (int i = 0; i < QA_MAXR; ++i) {
-        A[i] = i < r ? vars[b.aidx(i)] : 0.0;
+        A[i] = i < r ? vars.ac(b.aidx(i)) : 0.0;
         A2[i] = A[i] * A[i];
     }
     A[QA_MAXR] = A2[QA_MAXR] = 0.0;
@@ -384,9 +398,9 @@ QA_HD EQ eval_block_q(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q
 }
 
 template <class S, int R, int J> struct QStaticQ {
-    QA_HD static void run(double& s, double& sq, const QA_RO double* c, const double* A, const double* A2, LV<S> vars,
+    QA_HD static void run(double& s, double& sq, const QA_RO double* c, const double* A, const double* A2, VV<S> vars,
                           const BH& b) {
-        const double cj = vars[b.cidx(J)];
+        const double cj = vars.ac(b.cidx(J));
         const QA_RO double* cc = c + (1 << R) + J * (1 << (R - 1));
         s = s + cj * Fold<double, R - 1, J>::run(cc, A);
         sq = sq + (cj * cj) * Fold<double, R - 1, J, true>::run(cc, A2);
@@ -394,20 +408,20 @@ template <class S, int R, int J> struct QStaticQ {
     }
 };
 template <class S, int R> struct QStaticQ<S, R, R> {
-    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, LV<S>, const BH&) {}
+    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, VV<S>, const BH&) {}
 };
 
 template <class S, int R>
-QA_HD EQ block_static_q(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
+QA_HD EQ block_static_q(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
     const int k = b.k();
     double w = 1.0;
 #pragma unroll
     for (int q = 0; q < QA_MAXK; ++q)
-        if (q < k) w = w * vars[b.bidx(q)];
+        if (q < k) w = w * vars.bb(b.bidx(q));
     double A[R + 1], A2[R + 1];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        A[i] = vars[b.aidx(i)];
+        A[i] = vars.ac(b.aidx(i));
         A2[i] = A[i] * A[i];
     }
     A[R] = A2[R] = 0.0;
@@ -417,7 +431,7 @@ QA_HD EQ block_static_q(const BH& b, const QA_RO double* c, LV<S> vars, bool has
     return EQ{w * s, ldexp(w * w * sq, b.cexp())};
 }
 template <class T, class S, int R>
-QA_HD T block_any(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
+QA_HD T block_any(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
     if constexpr (std::is_same<T, EQ>::value) return block_static_q<S, R>(b, c, vars, has_q);
     else return block_static<T, S, R>(b, c, vars, has_q);
 }
@@ -427,7 +441,7 @@ QA_HD T block_any(const BH& b, const QA_RO double* c, LV<S> vars, bool has_q) {
 // (k + R lifted geometry values, the R-level fold, the k-pair product, the
 // final product), which acc_add uses for the ER estimate.
 template <class T, class S, int R, class AT>
-QA_HD void group_static(const QA_RO DevBlock* blocks, int b0, int b1, const QA_RO double* coefs, LV<S> vars, bool hq, AT& acc) {
+QA_HD void group_static(const QA_RO DevBlock* blocks, int b0, int b1, const QA_RO double* coefs, VV<S> vars, bool hq, AT& acc) {
     int bi = b0;
     for (; bi + 1 < b1; bi += 2) {
         const BH x = load_bh(blocks[bi]);
@@ -446,7 +460,7 @@ QA_HD void group_static(const QA_RO DevBlock* blocks, int b0, int b1, const QA_R
 // Evaluate one coefficient table: poly[k] = (1/denom) * sum over blocks with k
 // pairs.  All blocks with the same k have the same number of free slots r.
 template <class T, class S>
-QA_HD void eval_table(const QA_RO uint8_t* img, const QA_RO DevTable& tb, LV<S> vars, int n, T* poly,
+QA_HD void eval_table(const QA_RO uint8_t* img, const QA_RO DevTable& tb, VV<S> vars, int n, T* poly,
                       int slice = 0, int nslices = 1) {
     using AT = typename Acc<T>::type;
     using BT = typename BlockOf<T>::type;
@@ -517,7 +531,7 @@ QA_HD double kcoef(int n, int K) {
 // the double-double round-off.
 template <class T>
 QA_HD T eval_point(const QA_RO uint8_t* img, const QA_RO DevGraph& G, CLV<double> z,
-                   LV<typename GeoOf<T>::type> vars, LV<T> polys, double& cond_out, int slice = 0,
+                   VV<typename GeoOf<T>::type> vars, LV<T> polys, double& cond_out, int slice = 0,
                    int nslices = 1) {
     using S = typename GeoOf<T>::type;
     const int n = G.n;

@@ -146,13 +146,13 @@ __global__ void __launch_bounds__(256) k_sample(const uint8_t* __restrict__ img_
 // [element][lane]: geometry variables (QA_NVAR of the geometry type) then the
 // piece-result polynomials (npoly * QA_MAXN of the evaluation type).
 
-template <class T> __device__ __forceinline__ void lane_views(char* lds, int npoly, LV<typename GeoOf<T>::type>& vars,
+template <class T> __device__ __forceinline__ void lane_views(char* lds, int npoly, VV<typename GeoOf<T>::type>& vars,
                                                              LV<T>& polys) {
     using S = typename GeoOf<T>::type;
     const int lane = threadIdx.x, nt = blockDim.x;
     S* vbase = reinterpret_cast<S*>(lds);
     T* pbase = reinterpret_cast<T*>(lds + sizeof(S) * QA_NVAR * nt);
-    vars = LV<S>{vbase + lane, nt};
+    vars = vv(vbase + lane, nt);
     polys = LV<T>{pbase + lane, nt};
     (void)npoly;
 }
@@ -194,7 +194,8 @@ __global__ void __launch_bounds__(64) k_eval_fp64(const uint8_t* __restrict__ im
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const QA_RO DevGraph& G = dev_graph(img, graph);
-    LV<double> vars, polys;
+    VV<double> vars;
+    LV<double> polys;
     lane_views<double>(lds, G.npoly, vars, polys);
     double cond;
     f[i] = eval_point<double>(img, G, CLV<double>{z + i, (int)count}, vars, polys, cond);
@@ -208,7 +209,7 @@ __global__ void __launch_bounds__(64) k_eval_bound(const uint8_t* __restrict__ i
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const QA_RO DevGraph& G = dev_graph(img, graph);
-    LV<double> vars;
+    VV<double> vars;
     LV<EB> polys;
     lane_views<EB>(lds, G.npoly, vars, polys);
     double cond;
@@ -227,7 +228,7 @@ __global__ void __launch_bounds__(64) k_eval_est(const uint8_t* __restrict__ img
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const QA_RO DevGraph& G = dev_graph(img, graph);
-    LV<double> vars;
+    VV<double> vars;
     LV<ER> polys;
     lane_views<ER>(lds, G.npoly, vars, polys);
     double cond;
@@ -249,12 +250,13 @@ __global__ void __launch_bounds__(64) k_eval_dd(const uint8_t* __restrict__ img_
     double cond = 1.0, cond_dd;
     double mag = 0.0;
     if (err) {   // magnitude pass for the bound
-        LV<double> v1;
+        VV<double> v1;
         LV<EB> p1;
         lane_views<EB>(lds, G.npoly, v1, p1);
         mag = eval_point<EB>(img, G, CLV<double>{z + i, (int)count}, v1, p1, cond).a;
     }
-    LV<DD> vars, polys;
+    VV<DD> vars;
+    LV<DD> polys;
     lane_views<DD>(lds, G.npoly, vars, polys);
     DD r = eval_point<DD>(img, G, CLV<double>{z + i, (int)count}, vars, polys, cond_dd);
     f[i] = r.hi + r.lo;
@@ -366,7 +368,7 @@ struct Work {
     uint32_t grid;           // persistent waves of the double-double pass
     double* zbuf;            // per persistent wave: QA_MAXM * 64
     ER* pbuf;                // per persistent wave of the fused pass: piece results [QA_MAXPOLY * QA_MAXN][64]
-    double* vbuf;            // per persistent wave of the fused pass: geometry variables [QA_NVAR][64]
+    double* vbuf;            // per persistent wave of the fused pass: contraction matrix [QA_VAR_A][64]
     uint32_t tile, per_round, ng;
     uint64_t ntiles;
     uint64_t first;
@@ -416,21 +418,24 @@ __global__ void k_next_round(Work w) {
 // (candidates for the double-double pass).  A workgroup of kFusedWaves waves
 // (one per SIMD of a CU) takes a tile at a time, so that its waves walk the
 // same coefficient tables together and share the CU's scalar cache.  LDS
-// holds only the geometry variables (75 doubles per lane); the piece results
-// live in a per-wave global buffer.
+// holds the flows A, C of the geometry (20 doubles per lane, read about twice
+// as often as the contraction matrix); the contraction matrix and the piece
+// results live in per-wave global buffers.  Four waves per SIMD.
 constexpr int kFusedWaves = 4;
 constexpr int kFusedThreads = 64 * kFusedWaves;
 constexpr int kFusedOcc = 4;   // waves per SIMD the fused pass is compiled for
 __global__ void __launch_bounds__(kFusedThreads, kFusedOcc) k_fused(const uint8_t* __restrict__ img_, uint2 key, Work w) {
     const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
+    // LDS: the flows A, C of the workgroup's lanes, [20][256] doubles.  Between
+    // evaluations (after a barrier) its first bytes carry the workgroup's
+    // exchange: tile index, candidate counts, per-wave sums.
     extern __shared__ char lds[];
-    __shared__ uint32_t sh_t, sh_cnt[kFusedWaves];
-    __shared__ double sh_s[kFusedWaves][5];
-    __shared__ uint64_t sh_n[kFusedWaves][2];
+    uint32_t* sh_u = reinterpret_cast<uint32_t*>(lds);          // [0] tile, [1..4] counts
+    double* sh_s = reinterpret_cast<double*>(lds) + 8;            // [4][5] sums
+    uint64_t* sh_n = reinterpret_cast<uint64_t*>(lds) + 32;       // [4][2] counts
     const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
     const uint64_t gw = (uint64_t)blockIdx.x * kFusedWaves + wv;
-    LV<double> vars{w.vbuf + gw * (QA_NVAR * 64) + lane, 64};
-    (void)lds;
+    VV<double> vars{w.vbuf + gw * (QA_VAR_A * 64) + lane, 64, reinterpret_cast<double*>(lds) + tid, kFusedThreads};
     LV<ER> polys{w.pbuf + gw * (QA_MAXPOLY * QA_MAXN * 64) + lane, 64};
     double* zb = w.zbuf + gw * QA_MAXM * 64;
     uint64_t rt0;
@@ -444,9 +449,9 @@ __global__ void __launch_bounds__(kFusedThreads, kFusedOcc) k_fused(const uint8_
       const uint32_t x = (x0 + k) % kQueues;
       const uint32_t qlo = (uint32_t)((uint64_t)nr * x / kQueues), qhi = (uint32_t)((uint64_t)nr * (x + 1) / kQueues);
       for (;;) {
-        if (tid == 0) sh_t = atomicAdd(w.counter + x, 1u);
+        if (tid == 0) sh_u[0] = atomicAdd(w.counter + x, 1u);
         __syncthreads();
-        uint32_t t = __builtin_amdgcn_readfirstlane(sh_t);   // workgroup-uniform: scalar loads
+        uint32_t t = __builtin_amdgcn_readfirstlane(sh_u[0]);   // workgroup-uniform: scalar loads
         __syncthreads();
         if (t >= qhi - qlo) break;
         t += qlo;
@@ -497,12 +502,13 @@ __global__ void __launch_bounds__(kFusedThreads, kFusedOcc) k_fused(const uint8_
             }
             // candidate list: positions in wave order, then lane order
             const uint64_t mask = __ballot(flagged);
-            if (lane == 0) sh_cnt[wv] = (uint32_t)__popcll(mask);
+            __syncthreads();   // every wave is done with the variables
+            if (lane == 0) sh_u[1 + wv] = (uint32_t)__popcll(mask);
             __syncthreads();
             uint32_t off = nfl, tot = 0;
             for (int v = 0; v < kFusedWaves; ++v) {
-                if (v < wv) off += sh_cnt[v];
-                tot += sh_cnt[v];
+                if (v < wv) off += sh_u[1 + v];
+                tot += sh_u[1 + v];
             }
             if (flagged) {
                 const uint32_t pos = off + __popcll(mask & ((1ull << lane) - 1));
@@ -528,8 +534,9 @@ __global__ void __launch_bounds__(kFusedThreads, kFusedOcc) k_fused(const uint8_
         n = wave_sum_u64(n);
         bad = wave_sum_u64(bad);
         if (lane == 0) {
-            sh_s[wv][0] = s1.hi; sh_s[wv][1] = s1.lo; sh_s[wv][2] = s2.hi; sh_s[wv][3] = s2.lo; sh_s[wv][4] = s2g;
-            sh_n[wv][0] = n; sh_n[wv][1] = bad;
+            double* q = sh_s + 5 * wv;
+            q[0] = s1.hi; q[1] = s1.lo; q[2] = s2.hi; q[3] = s2.lo; q[4] = s2g;
+            sh_n[2 * wv] = n; sh_n[2 * wv + 1] = bad;
         }
         __syncthreads();
         if (tid == 0) {
@@ -538,11 +545,12 @@ __global__ void __launch_bounds__(kFusedThreads, kFusedOcc) k_fused(const uint8_
             double ag = 0.0;
             uint64_t an = 0, ab = 0;
             for (int v = 0; v < kFusedWaves; ++v) {
-                a1 = a1 + DD{sh_s[v][0], sh_s[v][1]};
-                a2 = a2 + DD{sh_s[v][2], sh_s[v][3]};
-                ag += sh_s[v][4];
-                an += sh_n[v][0];
-                ab += sh_n[v][1];
+                const double* q = sh_s + 5 * v;
+                a1 = a1 + DD{q[0], q[1]};
+                a2 = a2 + DD{q[2], q[3]};
+                ag += q[4];
+                an += sh_n[2 * v];
+                ab += sh_n[2 * v + 1];
             }
             Partial pr{};
             pr.s1_hi = a1.hi; pr.s1_lo = a1.lo; pr.s2_hi = a2.hi; pr.s2_lo = a2.lo;
@@ -675,7 +683,8 @@ __global__ void __launch_bounds__(64) k_fix_dd(const uint8_t* __restrict__ img_,
     const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
     extern __shared__ char lds[];
     const int lane = threadIdx.x;
-    LV<DD> vars, polys;
+    VV<DD> vars;
+    LV<DD> polys;
     lane_views<DD>(lds, 0, vars, polys);
     double* zb = w.zbuf + (uint64_t)blockIdx.x * QA_MAXM * 64;
     const uint32_t total = w.counter[kCSel], ns = w.counter[kCSlices];
@@ -780,7 +789,8 @@ __global__ void __launch_bounds__(64) k_vargrad(const uint8_t* __restrict__ img_
     extern __shared__ char lds[];
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const QA_RO DevGraph& G = dev_graph(img, graph);
-    LV<double> vars, polys;
+    VV<double> vars;
+    LV<double> polys;
     lane_views<double>(lds, G.npoly, vars, polys);
     // z after the polynomial region
     double* zb = reinterpret_cast<double*>(lds + lds_bytes_dev<double>(G.npoly, blockDim.x));
@@ -933,7 +943,7 @@ static WorkLayout work_layout(size_t ng, uint32_t tile, uint32_t per_round, uint
     L.fcond = take(8 * (size_t)per_round * tile);
     L.zbuf = take(8ull * QA_MAXM * 64 * grid);
     L.pbuf = take(sizeof(ER) * QA_MAXPOLY * QA_MAXN * 64 * (size_t)grid);
-    L.vbuf = take(sizeof(double) * QA_NVAR * 64 * (size_t)grid);
+    L.vbuf = take(sizeof(double) * QA_VAR_A * 64 * (size_t)grid);
     L.total = o;
     return L;
 }
@@ -1026,7 +1036,7 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     const uint2 key = make_uint2((uint32_t)seed, tag);
     int maxpoly = 1;
     for (size_t g = 0; g < ng; ++g) maxpoly = std::max(maxpoly, host_graph(*img, (uint32_t)g)->npoly);
-    const size_t lds_fp = 0, lds_dd = lds_bytes<DD>(maxpoly, 64);
+    const size_t lds_fp = sizeof(double) * (QA_NVAR - QA_VAR_A) * kFusedThreads, lds_dd = lds_bytes<DD>(maxpoly, 64);
     const uint64_t rounds = (ntiles + per_round - 1) / per_round;
     if (int rc = lds_attr(k_fused, lds_fp)) return rc;
     if (int rc = lds_attr(k_fix_dd, lds_dd)) return rc;
