@@ -58,8 +58,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--samples", type=int, default=1 << 23, help="samples per step over the 73 graphs")
-    ap.add_argument("--tile", type=int, default=256)
-    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0, help="0 with --grid 0: autotuned")
+    ap.add_argument("--grid", type=int, default=0, help="persistent waves; 0 with --tile 0: autotuned")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -93,6 +93,12 @@ def main():
         proc = ctx.Process(target=oracle_baseline, args=(q, args.cpu_seconds))
         proc.start()
 
+    tuned_ns = None
+    if args.tile == 0 and args.grid == 0:
+        # pick tile and grid on a pilot share of the budgets (outside the timed region)
+        args.tile, args.grid, tuned_ns = P.autotune(gset, img, budgets, SEED, 0, pilot=1 << 20)
+    elif args.tile == 0:
+        args.tile = 256
     work = torch.empty(P.work_bytes(gset, budgets, args.tile), dtype=torch.uint8, device="cuda:0")
     accs = []
     step = 0
@@ -154,10 +160,12 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "5-loop QED vertex graphs without lepton loops, class (5,0,0), 73 graphs; batched "
-                        "persistent hipGraph launch, FP64 with running error bound and double-double recompute",
+                        "persistent hipGraph launch (autotuned tile and grid), FP64 with a probabilistic round-off estimate "
+                        "and double-double recompute",
             "samples_per_step": int(per * ng),
             "tile": args.tile,
             "grid": args.grid,
+            "autotuned": tuned_ns is not None,
             "seed": SEED,
             "sigma_per_gpu_hour": sigma_gpu_hour,
             "class_value": val,

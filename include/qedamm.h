@@ -157,13 +157,27 @@ int qa_accumulate(const double* f, const double* logp, uint64_t count, qa_acc* a
  * work is split into rounds of at most 2^25 samples; one round is captured as
  * a hipGraph and replayed.  work (device) >= qa_work_bytes (same budgets and
  * tile; about 68 bytes per sample of a round).  tile = multiple of 64
- * (0 = 256); grid = persistent waves (0 = 4 per CU, max 2048).
+ * (0 = 256); grid = persistent waves (0 = 16 per CU, max 4096; rounded up to
+ * a multiple of 4: the fused pass runs workgroups of 4 waves).
  * fused_ms (host, nullable): receives the summed duration of the fused
  * kernel over all rounds, from HIP events on `stream`. */
 int qa_work_bytes(const qa_set* s, const uint64_t* budgets, uint32_t tile, size_t* bytes);
 int qa_integrate(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t first, uint64_t seed,
                  uint32_t tag, uint32_t tile, uint32_t grid, void* work, size_t work_bytes, qa_acc* acc,
                  double* fused_ms, void* stream);
+
+/* Autotuner of the batched form: for each candidate tile (256, 512, 1024
+ * samples; a fused workgroup of 256 lanes takes tile/256 samples per lane)
+ * and grid (16, 12 and 8 persistent waves per CU), runs qa_integrate twice on
+ * a pilot share of the budgets (about `pilot` samples in total, at least one
+ * per graph with a nonzero budget; 0 = 2^20) and times the fused kernel.
+ * Returns the fastest (tile, grid) and its time per sample in ns (nullable).
+ * work / work_bytes as for qa_integrate (candidates that do not fit are
+ * skipped; QA_ECAP if none fits); acc (device, ng records) is overwritten
+ * with pilot sums.  The pilot draws samples 0.. of the same streams. */
+int qa_autotune(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t seed, uint32_t tag,
+                uint64_t pilot, void* work, size_t work_bytes, qa_acc* acc, uint32_t* tile,
+                uint32_t* grid, double* ns_per_sample, void* stream);
 
 /* Variance gradient (pilot runs): for graph `graph`, samples first..first+
  * count-1 of stream (seed, tag): grad (device, 2^M doubles, accumulated +=)

@@ -59,6 +59,8 @@ def lib():
         L.qa_accumulate.argtypes = [vp, vp, u64, vp, vp]
         L.qa_work_bytes.argtypes = [vp, vp, u32, C.POINTER(sz)]
         L.qa_integrate.argtypes = [vp, vp, vp, u64, u64, u32, u32, u32, vp, sz, vp, vp, vp]
+        L.qa_autotune.argtypes = [vp, vp, vp, u64, u32, u64, vp, sz, vp, C.POINTER(u32), C.POINTER(u32),
+                                  C.POINTER(C.c_double), vp]
         L.qa_variance_grad.argtypes = [vp, u32, u64, u32, u64, u64, vp, vp, vp]
         L.qa_graph_flops.argtypes = [vp, u32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.qa_dirac_trace.argtypes = [vp, i32, C.POINTER(C.c_double)]
@@ -281,6 +283,22 @@ def integrate(gset, img, budgets, seed, tag=0, tile=0, grid=0, work=None, acc=No
                               _ptr(work), work.numel(), _ptr(acc), C.byref(ms) if timing else None,
                               _stream(stream)), "qa_integrate")
     return (acc, ms.value) if timing else acc
+
+
+def autotune(gset, img, budgets, seed, tag=0, pilot=0, work=None, stream=None):
+    """Pick the batched form's (tile, grid) by timing the fused pass on a pilot
+    share of the budgets.  Returns (tile, grid, ns per sample)."""
+    import torch
+    b = np.ascontiguousarray(budgets, dtype=np.uint64)
+    dev = img.buf.device
+    if work is None:
+        work = torch.empty(work_bytes(gset, b, 256), dtype=torch.uint8, device=dev)
+    acc = new_acc(len(gset), dev)
+    tile, grid, ns = C.c_uint32(), C.c_uint32(), C.c_double()
+    _check(lib().qa_autotune(gset.h, img.ptr, b.ctypes.data_as(C.c_void_p), seed, tag, pilot, _ptr(work),
+                             work.numel(), _ptr(acc), C.byref(tile), C.byref(grid), C.byref(ns), _stream(stream)),
+           "qa_autotune")
+    return tile.value, grid.value, ns.value
 
 
 def variance_grad(img, graph, seed, tag, first, count, grad=None, w2sum=None, stream=None):

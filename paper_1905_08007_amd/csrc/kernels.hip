@@ -1114,6 +1114,55 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     return QA_OK;
 }
 
+// Autotuner of the batched form: times the fused pass on a pilot share of the
+// budgets for each candidate (tile, grid) and returns the fastest per sample.
+// A fused workgroup of 256 lanes takes tile / 256 samples per lane (the
+// samples per thread); grid is the number of persistent waves.
+extern "C" int qa_autotune(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t seed, uint32_t tag,
+                           uint64_t pilot, void* work, size_t work_bytes, qa_acc* acc, uint32_t* tile_out,
+                           uint32_t* grid_out, double* ns_per_sample, void* stream) {
+    if (!s || !dev || !budgets || !work || !acc || !tile_out || !grid_out) return qa_fail(QA_EINVAL, "NULL argument");
+    const size_t ng = qa_set_size(s);
+    double total = 0.0;
+    for (size_t g = 0; g < ng; ++g) total += (double)budgets[g];
+    if (total <= 0.0) return qa_fail(QA_EINVAL, "all budgets are zero");
+    if (pilot == 0) pilot = 1ull << 20;
+    std::vector<uint64_t> pb(ng, 0);
+    uint64_t ptot = 0;
+    for (size_t g = 0; g < ng; ++g) {
+        if (budgets[g] == 0) continue;
+        pb[g] = std::max<uint64_t>(1, (uint64_t)((double)budgets[g] * (double)pilot / total));
+        ptot += pb[g];
+    }
+    const uint32_t full = default_grid(), cu4 = full / kFusedOcc;   // 4 waves per CU = one per SIMD
+    const uint32_t tiles[3] = {256, 512, 1024};
+    const uint32_t grids[3] = {full, std::min<uint32_t>(kMaxWaves, 3 * cu4), 2 * cu4};
+    double best = 1e300;
+    uint32_t bt = 0, bg = 0;
+    for (uint32_t tile : tiles) {
+        const size_t need = work_layout(ng, tile, tiles_per_round(count_tiles(pb.data(), ng, tile), tile), kMaxWaves).total;
+        if (need > work_bytes) continue;
+        for (uint32_t grid : grids) {
+            double ms = 0.0;
+            for (int rep = 0; rep < 2; ++rep) {   // the first run warms caches and instantiates the graphs
+                if (int rc = qa_integrate(s, dev, pb.data(), 0, seed, tag, tile, grid, work, work_bytes, acc, &ms, stream))
+                    return rc;
+            }
+            const double t = ms * 1e6 / (double)ptot;
+            if (t < best) {
+                best = t;
+                bt = tile;
+                bg = grid;
+            }
+        }
+    }
+    if (bt == 0) return qa_fail(QA_ECAP, "work buffer too small for the pilot");
+    *tile_out = bt;
+    *grid_out = bg;
+    if (ns_per_sample) *ns_per_sample = best;
+    return QA_OK;
+}
+
 extern "C" int qa_variance_grad(const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, uint64_t first,
                                 uint64_t count, double* grad, double* w2sum, void* stream) {
     auto* img = image_of(dev);

@@ -344,3 +344,17 @@ def test_batched_5loop_matches_plain():
         wd = fd * ip
         assert np.all(np.abs(w[good] - wd[good]) <= 1e-10 * np.maximum(np.abs(wd[good]), scale))
     assert all(int(a[g]["n"]) == 0 for g in range(len(gs)) if g not in (1, 40, 72))
+
+
+def test_autotune_picks_a_candidate_and_integrates():
+    gs, s, p, img, og = setup(2)
+    budgets = [30_000, 20_000, 10_000, 5_000]
+    tile, grid, ns = P.autotune(s, img, budgets, seed=5, tag=0, pilot=1 << 15)
+    assert tile in (256, 512, 1024) and grid > 0 and grid % 4 == 0 and ns > 0
+    a = P.read_acc(P.integrate(s, img, budgets, seed=5, tag=0, tile=tile, grid=grid))
+    b = P.read_acc(P.integrate(s, img, budgets, seed=5, tag=0))
+    sync()
+    for x, y in zip(a, b):
+        assert int(x["n"]) == int(y["n"]) and int(x["n_flagged"]) == int(y["n_flagged"])
+        s1x, s1y = x["s1_hi"] + x["s1_lo"], y["s1_hi"] + y["s1_lo"]
+        assert abs(s1x - s1y) <= 1e-12 * math.sqrt((y["s2_hi"] + y["s2_lo"]) * max(1, int(y["n"])))
