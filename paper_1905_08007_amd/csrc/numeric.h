@@ -89,6 +89,14 @@ QA_HD DD two_prod(double a, double b) {
     double e = fma(a, b, -p);
     return DD{p, e};
 }
+// double-double plus double (accurate: two_sum of the high parts)
+QA_HD DD add_d(DD a, double b) {
+#pragma clang fp contract(off)
+
+    DD s = two_sum(a.hi, b);
+    s.lo += a.lo;
+    return quick_two_sum(s.hi, s.lo);
+}
 QA_HD DD dd(double x) {
 #pragma clang fp contract(off)
  return DD{x, 0.0}; }
@@ -206,7 +214,7 @@ QA_HD ERAcc acc_zero(ERAcc*) { return ERAcc{DD{0.0, 0.0}, 0.0}; }
 QA_HD void acc_add(double& s, double x) { s += x; }
 QA_HD void acc_add(EBAcc& s, EB x) {
 #pragma clang fp contract(off)
-    s.v = s.v + dd(x.v);
+    s.v = add_d(s.v, x.v);
     s.a += x.a;
 }
 QA_HD void acc_add(DD& s, DD x) { s = s + x; }
@@ -215,7 +223,7 @@ QA_HD void acc_add(DD& s, DD x, int) { s = s + x; }
 QA_HD void acc_add(EBAcc& s, EB x, int) { acc_add(s, x); }
 QA_HD void acc_add(ERAcc& s, EQ x, int nb) {
 #pragma clang fp contract(off)
-    s.v = s.v + dd(x.v);
+    s.v = add_d(s.v, x.v);
     s.q += (double)nb * x.q;
 }
 QA_HD double acc_get(double s) { return s; }
