@@ -52,6 +52,27 @@ def oracle_baseline(q, seconds):
         q.put({"error": repr(e)})
 
 
+def measured_traffic(samples_per_launch):
+    """HBM-side bytes of one fused launch, from the committed FETCH_SIZE / WRITE_SIZE
+    passes (profiles/k_fused_traffic.json, scaled by a plain-copy calibration), or
+    None when the kernel sources changed since those counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "k_fused_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(root, src), "rb") as fh:
+                h.update(fh.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["bytes_per_sample"] * samples_per_launch
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,7 +204,7 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(per * ng),
         },
         "cpu_baseline": cpu,
     }
