@@ -49,17 +49,11 @@ typedef struct qa_acc {
     double s2_hi, s2_lo;
     uint64_t n_flagged;   /* points recomputed in double-double */
     uint64_t n_bad;       /* non-finite or underflowed points, excluded */
-    uint64_t n_residual;  /* flagged points whose double-double bound still exceeds 1e-10 |f| (kept, counted) */
+    uint64_t n_residual;  /* recomputed points whose double-double estimate still exceeds 1e-10 of the weight scale (kept, counted) */
 } qa_acc;
 
 typedef struct qa_set qa_set;   /* graphs + forests + integrand tables (host) */
-typedef struct qa_pdf qa_pdf;   /* Algorithmic FP64 operation count of one plain evaluation of graph i's
- * integrand (graph polynomials of every piece, every coefficient-table block
- * with its multilinear fold, forest-term combination) plus the sector
- * sampler; an FMA counts 2.  Used for the roofline of the integrand kernel. */
-int qa_graph_flops(const qa_set* s, uint32_t graph, double* eval_flops, double* sample_flops);
-
-/* Deg and W tables of eq. (1) (host) */
+typedef struct qa_pdf qa_pdf;   /* Deg and W tables of eq. (1) (host) */
 
 const char* qa_last_error(void);
 
@@ -94,6 +88,17 @@ int qa_set_stats(const qa_set* s, uint64_t* nterms, uint64_t* nblocks, uint64_t*
  * with its multilinear fold, forest-term combination) plus the sector
  * sampler; an FMA counts 2.  Used for the roofline of the integrand kernel. */
 int qa_graph_flops(const qa_set* s, uint32_t graph, double* eval_flops, double* sample_flops);
+
+/* Per-graph budgets from a pilot (host arrays; pilot = ng qa_acc records read
+ * back from the device): N_g = floor + share of (total - ng*floor) in
+ * proportion to mu_g sigma_g / sqrt(c_g) (sigma_g the pilot's per-sample
+ * standard deviation of w, c_g the flops of one sample from qa_graph_flops),
+ * the Neyman allocation that minimises the variance of the set total at a
+ * fixed cost; remainders by largest fraction (ties: lower graph index), so
+ * the budgets sum to total exactly.  All weights zero (or non-finite): equal
+ * shares.  QA_EINVAL if total < ng*floor.  The paper sums per-graph Monte
+ * Carlo integrals (Table 1) and does not state its budgets. */
+int qa_allocate_budgets(const qa_set* s, const qa_acc* pilot, uint64_t total, uint64_t floor, uint64_t* out);
 
 /* Deg and W tables of eq. (1) for every graph of the set.  deg == NULL: the
  * default Deg rule (parametric UV degree of the I-closure, minimised over the

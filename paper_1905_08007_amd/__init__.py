@@ -59,6 +59,7 @@ def lib():
         L.qa_accumulate.argtypes = [vp, vp, u64, vp, vp]
         L.qa_work_bytes.argtypes = [vp, vp, u32, C.POINTER(sz)]
         L.qa_integrate.argtypes = [vp, vp, vp, u64, u64, u32, u32, u32, vp, sz, vp, vp, vp]
+        L.qa_allocate_budgets.argtypes = [vp, vp, u64, u64, vp]
         L.qa_autotune.argtypes = [vp, vp, vp, u64, u32, u64, vp, sz, vp, C.POINTER(u32), C.POINTER(u32),
                                   C.POINTER(C.c_double), vp]
         L.qa_variance_grad.argtypes = [vp, u32, u64, u32, u64, u64, vp, vp, vp]
@@ -283,6 +284,18 @@ def integrate(gset, img, budgets, seed, tag=0, tile=0, grid=0, work=None, acc=No
                               _ptr(work), work.numel(), _ptr(acc), C.byref(ms) if timing else None,
                               _stream(stream)), "qa_integrate")
     return (acc, ms.value) if timing else acc
+
+
+def allocate_budgets(gset, pilot, total, floor=0):
+    """Per-graph budgets from pilot sums (ACC_DTYPE records, e.g. read_acc of a
+    pilot integrate): Neyman allocation mu sigma / sqrt(cost), floored, summing to total."""
+    rec = np.ascontiguousarray(pilot, dtype=ACC_DTYPE)
+    if rec.shape != (len(gset),):
+        raise RuntimeError("pilot must hold one record per graph")
+    out = np.zeros(len(gset), dtype=np.uint64)
+    _check(lib().qa_allocate_budgets(gset.h, rec.ctypes.data_as(C.c_void_p), int(total), int(floor),
+                                     out.ctypes.data_as(C.c_void_p)), "qa_allocate_budgets")
+    return out
 
 
 def autotune(gset, img, budgets, seed, tag=0, pilot=0, work=None, stream=None):

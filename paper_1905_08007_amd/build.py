@@ -13,15 +13,27 @@ SOURCES = ["host.cpp", "tables.cpp", "capi.cpp", "kernels.hip"]
 ARCH = os.environ.get("QA_OFFLOAD_ARCH", "gfx950")
 
 
-def build(verbose=False, jobs=8):
+def _newest_header():
+    hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    hdrs.append(os.path.join(HERE, "..", "include", "qedamm.h"))
+    return max(os.path.getmtime(h) for h in hdrs)
+
+
+def build(verbose=False, jobs=8, incremental=False):
+    """Compile and link the library.  incremental=True (development only) skips
+    objects newer than their source and every header."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
     procs = []
     common = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result"]
+    newest_h = _newest_header() if incremental else None
     for src in SOURCES:
         obj = os.path.join(CSRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
         path = os.path.join(CSRC, src)
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(path), newest_h):
+            objs.append(obj)
+            continue
         if src.endswith(".hip"):
             cmd = [hipcc, "-x", "hip", f"--offload-arch={ARCH}", "-ffp-contract=fast-honor-pragmas",
                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -53,4 +65,4 @@ def build(verbose=False, jobs=8):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

@@ -249,6 +249,52 @@ extern "C" int qa_graph_flops(const qa_set* s, uint32_t graph, double* eval_flop
     return QA_OK;
 }
 
+// Budgets across graphs from a pilot (Neyman allocation: the variance of the
+// set total, sum mu_g^2 sigma_g^2 / N_g, is smallest at a fixed cost sum c_g N_g
+// when N_g is proportional to mu_g sigma_g / sqrt(c_g)); every graph gets at
+// least `floor` samples and the remainder is split by largest remainders.
+extern "C" int qa_allocate_budgets(const qa_set* s, const qa_acc* pilot, uint64_t total, uint64_t floor,
+                                   uint64_t* out) {
+    if (!s || !pilot || !out) return fail(QA_EINVAL, "NULL argument");
+    const size_t ng = s->graphs.size();
+    if (ng == 0) return QA_OK;
+    if (floor > total / ng) return fail(QA_EINVAL, "total below floor * graphs");
+    std::vector<double> wt(ng, 0.0);
+    double sw = 0.0;
+    for (size_t g = 0; g < ng; ++g) {
+        const qa_acc& a = pilot[g];
+        double sd = 0.0;
+        if (a.n >= 2) {
+            const double n = (double)a.n, m = (a.s1_hi + a.s1_lo) / n, m2 = (a.s2_hi + a.s2_lo) / n;
+            sd = std::sqrt(std::max(0.0, m2 - m * m));
+        }
+        double fe = 0.0, fs = 0.0;
+        qa_graph_flops(s, (uint32_t)g, &fe, &fs);
+        wt[g] = s->graphs[g].g.mult * sd / std::sqrt(std::max(1.0, fe + fs));
+        sw += wt[g];
+    }
+    const uint64_t rest = total - floor * ng;
+    if (!(sw > 0.0) || !std::isfinite(sw)) {
+        for (size_t g = 0; g < ng; ++g) wt[g] = 1.0;
+        sw = (double)ng;
+    }
+    std::vector<std::pair<double, size_t>> rem(ng);
+    uint64_t given = 0;
+    for (size_t g = 0; g < ng; ++g) {
+        const double share = (double)rest * wt[g] / sw;
+        const uint64_t base = (uint64_t)std::floor(share);
+        out[g] = floor + base;
+        given += base;
+        rem[g] = {share - (double)base, g};
+    }
+    // largest remainders first; ties by graph index
+    std::stable_sort(rem.begin(), rem.end(), [](const std::pair<double, size_t>& a, const std::pair<double, size_t>& b) {
+        return a.first > b.first;
+    });
+    for (size_t i = 0; given < rest && i < ng; ++i, ++given) out[rem[i].second] += 1;
+    return QA_OK;
+}
+
 extern "C" int qa_pdf_create(const qa_set* s, const double* deg, qa_pdf** out) {
     try {
         if (!s || !out) return fail(QA_EINVAL, "NULL argument");

@@ -238,6 +238,22 @@ def test_variance_grad_matches_oracle():
     assert np.allclose(g, go, rtol=1e-8, atol=1e-10 * np.max(np.abs(go)))
 
 
+def test_variance_grad_4loop_matches_oracle():
+    """The pilot's backward kernel at 4 loops (configuration of the 4-loop pilot):
+    E[w^2] and its gradient over the graph's Deg table against the oracle on
+    the same Philox samples (tag 1 = pilot).  FP64 integrand on the GPU, so the
+    tolerance is the FP64 round-off of w^2, not the 2-loop 1e-8."""
+    gs, s, p, img, og = setup(4)
+    gi, seed, tag, count = 100, 4, 1, 24
+    m2, g = P.variance_and_grad(s, p, img, gi, seed, tag, 0, count)
+    smp = mc.graph_samples(og[gi], gi, seed, 0, count, tag=tag)
+    D, _ = p.tables(gi)
+    go = mc.variance_grad(smp, D, 12)
+    m2o = sum(x[3] * x[3] for x in smp) / count
+    assert abs(m2 - m2o) < 1e-7 * m2o
+    assert np.allclose(g, go, rtol=1e-6, atol=1e-9 * np.max(np.abs(go)))
+
+
 def test_edge_cases():
     gs, s, p, img, og = setup(2)
     z = torch.empty((6, 0), dtype=torch.float64, device="cuda")
@@ -314,6 +330,30 @@ def test_sample_and_eval_5loop_bench_stream():
             assert abs(f - pt["f"]) <= 1e-9 * abs(pt["f"]), (gi, pt["sample"], f, pt["f"])
 
 
+def _check_batched_graph(img, gi, seed, tag, b, x):
+    """Reproduce one graph of a single-round batched run with the plain entry
+    points (same Philox points; the estimate flag; the double-double recompute
+    selected against max(|w|, rms of the accurate weights)) and compare."""
+    z, lp, _ = P.sample_pdf(img, gi, seed, tag, 0, b)
+    fe, ee, flag = P.eval_integrand(img, gi, z, P.QA_FP64_EST)
+    fd, _, _ = P.eval_integrand(img, gi, z, P.QA_DD)
+    sync()
+    fe, ee, flag, fd = fe.cpu().numpy(), ee.cpu().numpy(), flag.cpu().numpy().astype(bool), fd.cpu().numpy()
+    ip = np.exp(-lp.cpu().numpy())
+    w0 = fe * ip
+    good = np.isfinite(w0)
+    acc_ok = good & ~flag
+    scale = math.sqrt(math.fsum(w0[acc_ok] ** 2) / max(1, good.sum()))
+    need = flag & good & ~(ee * ip <= 1e-11 * np.maximum(np.abs(w0), scale))
+    w = np.where(need, fd, fe) * ip
+    assert int(x["n"]) == good.sum() and int(x["n_flagged"]) == int(need.sum())
+    s1 = math.fsum(w[good])
+    assert abs(x["s1_hi"] + x["s1_lo"] - s1) <= 1e-12 * math.fsum(np.abs(w[good]))
+    # every accepted FP64 weight is within 1e-10 of the scale of the double-double one
+    wd = fd * ip
+    assert np.all(np.abs(w[good] - wd[good]) <= 1e-10 * np.maximum(np.abs(wd[good]), scale))
+
+
 def test_batched_5loop_matches_plain():
     gs, s, p, img = setup5()
     budgets = np.zeros(len(gs), dtype=np.uint64)
@@ -322,28 +362,25 @@ def test_batched_5loop_matches_plain():
     sync()
     a = P.read_acc(acc)
     for gi in (1, 40, 72):
-        b = int(budgets[gi])
-        z, lp, _ = P.sample_pdf(img, gi, 5, 0, 0, b)
-        fe, ee, flag = P.eval_integrand(img, gi, z, P.QA_FP64_EST)
-        fd, _, _ = P.eval_integrand(img, gi, z, P.QA_DD)
-        sync()
-        fe, ee, flag, fd = fe.cpu().numpy(), ee.cpu().numpy(), flag.cpu().numpy().astype(bool), fd.cpu().numpy()
-        ip = np.exp(-lp.cpu().numpy())
-        # the batched selection: estimate on w against max(|w|, rms of the accurate weights)
-        w0 = fe * ip
-        good = np.isfinite(w0)
-        acc_ok = good & ~flag
-        scale = math.sqrt(math.fsum(w0[acc_ok] ** 2) / max(1, good.sum()))
-        need = flag & good & ~(ee * ip <= 1e-11 * np.maximum(np.abs(w0), scale))
-        w = np.where(need, fd, fe) * ip
-        x = a[gi]
-        assert int(x["n"]) == good.sum() and int(x["n_flagged"]) == int(need.sum())
-        s1 = math.fsum(w[good])
-        assert abs(x["s1_hi"] + x["s1_lo"] - s1) <= 1e-12 * math.fsum(np.abs(w[good]))
-        # every accepted FP64 weight is within 1e-10 of the scale of the double-double one
-        wd = fd * ip
-        assert np.all(np.abs(w[good] - wd[good]) <= 1e-10 * np.maximum(np.abs(wd[good]), scale))
+        _check_batched_graph(img, gi, 5, 0, int(budgets[gi]), a[gi])
     assert all(int(a[g]["n"]) == 0 for g in range(len(gs)) if g not in (1, 40, 72))
+
+
+def test_three_loop_pilot_budgets_batched():
+    """3-loop flow: a pilot run (tag 1), Neyman budgets from its sums, the
+    batched production run (tag 0) with those uneven budgets."""
+    gs, s, p, img, og = setup(3)
+    pilot = P.read_acc(P.integrate(s, img, [2048] * len(gs), seed=3, tag=1))
+    sync()
+    assert all(int(x["n"]) + int(x["n_bad"]) == 2048 for x in pilot)
+    budgets = P.allocate_budgets(s, pilot, 150_000, 512)
+    assert int(budgets.sum()) == 150_000 and budgets.min() >= 512 and budgets.max() > 2 * budgets.min()
+    a = P.read_acc(P.integrate(s, img, budgets, seed=3, tag=0))
+    sync()
+    for g in range(len(gs)):
+        assert int(a[g]["n"]) + int(a[g]["n_bad"]) == int(budgets[g])
+    for gi in (0, 13, 27):
+        _check_batched_graph(img, gi, 3, 0, int(budgets[gi]), a[gi])
 
 
 def test_autotune_picks_a_candidate_and_integrates():

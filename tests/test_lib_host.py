@@ -100,3 +100,35 @@ def test_errors_are_reported():
     s = P.build_forests(P.enumerate_graphs(1))
     with pytest.raises(RuntimeError):
         P.pdf_create(s, deg=[np.zeros(8)])
+
+
+def test_allocate_budgets_neyman():
+    import paper_1905_08007_amd as P
+    gs = P.enumerate_graphs(2)
+    s = P.build_forests(gs, 2)
+    ng = len(gs)
+    rec = np.zeros(ng, dtype=P.ACC_DTYPE)
+    rng = np.random.default_rng(7)
+    sd = np.array([0.5, 2.0, 0.0, 1.0])
+    for g in range(ng):
+        n = 1000
+        rec[g]["n"] = n
+        mean = rng.normal()
+        rec[g]["s1_hi"] = mean * n
+        rec[g]["s2_hi"] = (sd[g] ** 2 + mean ** 2) * n
+    total, floor = 100_003, 1000
+    out = P.allocate_budgets(s, rec, total, floor)
+    assert int(out.sum()) == total and np.all(out >= floor)
+    # independent computation of the Neyman shares
+    mult = np.array([g.mult for g in gs], dtype=float)
+    cost = np.array([sum(s.flops(g)) for g in range(ng)])
+    sdh = np.sqrt(np.maximum(0.0, rec["s2_hi"] / 1000 - (rec["s1_hi"] / 1000) ** 2))
+    w = mult * sdh / np.sqrt(cost)
+    share = (total - floor * ng) * w / w.sum()
+    assert np.all(np.abs(out - floor - share) < 1.0 + 1e-9)
+    assert out[2] == floor  # zero variance: only the floor
+    # all-zero pilot: equal shares
+    out0 = P.allocate_budgets(s, np.zeros(ng, dtype=P.ACC_DTYPE), 4003, 0)
+    assert int(out0.sum()) == 4003 and out0.max() - out0.min() <= 1
+    with pytest.raises(RuntimeError):
+        P.allocate_budgets(s, rec, 10, 1000)
