@@ -443,13 +443,26 @@ QA_HD T block_any(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
 template <class T, class S, int R, class AT>
 QA_HD void group_static(const QA_RO DevBlock* blocks, int b0, int b1, const QA_RO double* coefs, VV<S> vars, bool hq, AT& acc) {
     int bi = b0;
-    for (; bi + 1 < b1; bi += 2) {
-        const BH x = load_bh(blocks[bi]);
-        const BH y = load_bh(blocks[bi + 1]);
-        const T vx = block_any<T, S, R>(x, coefs + x.coef(), vars, hq);
-        const T vy = block_any<T, S, R>(y, coefs + y.coef(), vars, hq);
-        acc_add(acc, vx, 2 * (x.k() + R) + 3);
-        acc_add(acc, vy, 2 * (y.k() + R) + 3);
+    if (bi + 1 < b1) {
+        // software pipeline: the next pair's headers are loaded (clamped to the
+        // last pair, always in range) before this pair is evaluated, so their
+        // latency overlaps this pair's coefficient loads
+        BH x = load_bh(blocks[bi]);
+        BH y = load_bh(blocks[bi + 1]);
+        for (;;) {
+            const int nb = bi + 2;
+            const int pf = nb + 1 < b1 ? nb : b1 - 2;
+            const BH xn = load_bh(blocks[pf]);
+            const BH yn = load_bh(blocks[pf + 1]);
+            const T vx = block_any<T, S, R>(x, coefs + x.coef(), vars, hq);
+            const T vy = block_any<T, S, R>(y, coefs + y.coef(), vars, hq);
+            acc_add(acc, vx, 2 * (x.k() + R) + 3);
+            acc_add(acc, vy, 2 * (y.k() + R) + 3);
+            bi = nb;
+            if (bi + 1 >= b1) break;
+            x = xn;
+            y = yn;
+        }
     }
     if (bi < b1) {
         const BH x = load_bh(blocks[bi]);
