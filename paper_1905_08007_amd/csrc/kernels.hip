@@ -352,6 +352,7 @@ struct FlagEntry {
     uint8_t residual; // double-double estimate still above 1e-10 of the scale
     uint8_t pad[2];
 };
+static_assert(sizeof(DD) == sizeof(ER), "the DD pass reuses the piece-result buffer of the fused pass");
 struct Work {
     uint32_t* counter;       // [0..7] tile queues (one per XCD), [8] round, [9] selected entries, [10] fix chunks
     uint64_t* gtile0;        // per graph: first global tile index (ng + 1 entries)
@@ -367,7 +368,7 @@ struct Work {
     double* fcond;           // double-double pass: geometry conditioning per selected entry
     uint32_t grid;           // persistent waves of the double-double pass
     double* zbuf;            // per persistent wave: QA_MAXM * 64
-    ER* pbuf;                // per persistent wave of the fused pass: piece results [QA_MAXPOLY * QA_MAXN][64]
+    ER* pbuf;                // per persistent wave: piece results [QA_MAXPOLY * QA_MAXN][64] (ER, or DD in the DD pass)
     double* vbuf;            // per persistent wave of the fused pass: contraction matrix [QA_VAR_A][64]
     uint32_t tile, per_round, ng;
     uint64_t ntiles;
@@ -681,12 +682,16 @@ __global__ void __launch_bounds__(64) k_compact(Work w) {
 // slices in order.
 __global__ void __launch_bounds__(64) k_fix_dd(const uint8_t* __restrict__ img_, uint2 key, Work w) {
     const QA_RO uint8_t* img = (const QA_RO uint8_t*)img_;
+    // LDS holds the flows A, C (20 double-doubles per lane, 20 KB per wave); the
+    // contraction matrix and the piece results use the per-wave global buffers
+    // of the fused pass (which does not run concurrently), so that eight waves
+    // fit on a CU.
     extern __shared__ char lds[];
     const int lane = threadIdx.x;
-    VV<DD> vars;
-    LV<DD> polys;
-    lane_views<DD>(lds, 0, vars, polys);
-    double* zb = w.zbuf + (uint64_t)blockIdx.x * QA_MAXM * 64;
+    const uint64_t gw = blockIdx.x;
+    VV<DD> vars{reinterpret_cast<DD*>(w.vbuf) + gw * (QA_VAR_A * 64) + lane, 64, reinterpret_cast<DD*>(lds) + lane, 64};
+    LV<DD> polys{reinterpret_cast<DD*>(w.pbuf) + gw * (QA_MAXPOLY * QA_MAXN * 64) + lane, 64};
+    double* zb = w.zbuf + gw * QA_MAXM * 64;
     const uint32_t total = w.counter[kCSel], ns = w.counter[kCSlices];
     const uint32_t items = (total + 63) / 64 * ns;
     for (;;) {
@@ -943,7 +948,7 @@ static WorkLayout work_layout(size_t ng, uint32_t tile, uint32_t per_round, uint
     L.fcond = take(8 * (size_t)per_round * tile);
     L.zbuf = take(8ull * QA_MAXM * 64 * grid);
     L.pbuf = take(sizeof(ER) * QA_MAXPOLY * QA_MAXN * 64 * (size_t)grid);
-    L.vbuf = take(sizeof(double) * QA_VAR_A * 64 * (size_t)grid);
+    L.vbuf = take(sizeof(DD) * QA_VAR_A * 64 * (size_t)grid);   // double in the fused pass, DD in the DD pass
     L.total = o;
     return L;
 }
@@ -1034,9 +1039,10 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     w.ntiles = ntiles;
     w.first = first;
     const uint2 key = make_uint2((uint32_t)seed, tag);
-    int maxpoly = 1;
-    for (size_t g = 0; g < ng; ++g) maxpoly = std::max(maxpoly, host_graph(*img, (uint32_t)g)->npoly);
-    const size_t lds_fp = sizeof(double) * (QA_NVAR - QA_VAR_A) * kFusedThreads, lds_dd = lds_bytes<DD>(maxpoly, 64);
+    for (size_t g = 0; g < ng; ++g)
+        if (host_graph(*img, (uint32_t)g)->npoly > QA_MAXPOLY) return qa_fail(QA_ENOTSUP, "too many piece-result slots");
+    const size_t lds_fp = sizeof(double) * (QA_NVAR - QA_VAR_A) * kFusedThreads,
+                 lds_dd = sizeof(DD) * (QA_NVAR - QA_VAR_A) * 64;
     const uint64_t rounds = (ntiles + per_round - 1) / per_round;
     if (int rc = lds_attr(k_fused, lds_fp)) return rc;
     if (int rc = lds_attr(k_fix_dd, lds_dd)) return rc;
