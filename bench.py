@@ -73,6 +73,33 @@ def measured_traffic(samples_per_launch):
     return rec["bytes_per_sample"] * samples_per_launch
 
 
+def plain_path(P, img, graphs, per_graph, first):
+    """The plain per-graph FP64 path on the same GPU, for comparison with the
+    batched form: for each graph in turn qa_sample_pdf -> qa_eval_integrand
+    (FP64) -> qa_accumulate, per_graph samples each (outside the timed region
+    of the batched form).  Returns its evals/s and sigma per GPU-hour."""
+    import torch
+    ng = len(graphs)
+    acc = P.new_acc(ng)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(ng):
+        z, lp, _ = P.sample_pdf(img, g, SEED, 0, first, per_graph)
+        f, _, _ = P.eval_integrand(img, g, z, P.QA_FP64)
+        P.accumulate(f, lp, acc, g)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    a = P.read_acc(acc)
+    var = 0.0
+    for i, gr in enumerate(graphs):
+        n = float(a["n"][i])
+        m = (a["s1_hi"][i] + a["s1_lo"][i]) / n
+        v = ((a["s2_hi"][i] + a["s2_lo"][i]) / n - m * m) / (n - 1)
+        var += gr.mult ** 2 * v
+    return {"evals_per_s": per_graph * ng / dt, "sigma_per_gpu_hour": math.sqrt(var) * math.sqrt(dt / 3600.0),
+            "samples_per_graph": per_graph}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +111,8 @@ def main():
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-samples", type=int, default=1 << 16,
+                    help="samples per graph of the plain per-graph FP64 comparison (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
@@ -161,6 +190,14 @@ def main():
     sigma_gpu_hour = sigma * math.sqrt(dt / 3600.0)
     achieved = eval_flops_step * args.steps / (fused_ms * 1e-3) / 1e12
 
+    plain = None
+    if args.plain_samples > 0:
+        plain = plain_path(P, img, graphs, args.plain_samples, first=step * per)
+        # Both paths sample the same distribution; the per-sample variance of these
+        # heavy-tailed weights is far better estimated by the batched run's N, so the
+        # comparison at equal per-sample sigma is sigma_hour * sqrt(rate ratio).
+        plain["sigma_per_gpu_hour_at_batched_variance"] = sigma_gpu_hour * math.sqrt(evals_s / plain["evals_per_s"])
+
     cpu = None
     if proc is not None:
         proc.join(timeout=600)
@@ -189,6 +226,7 @@ def main():
             "autotuned": tuned_ns is not None,
             "seed": SEED,
             "sigma_per_gpu_hour": sigma_gpu_hour,
+            "plain_per_graph_fp64": plain,
             "class_value": val,
             "class_sigma": sigma,
             "flagged_fraction": float(tot["flag"].sum() / max(1.0, tot["n"].sum())),
