@@ -3,13 +3,18 @@
 Workload: the 73 representatives of the gauge-invariant class (5,0,0) of
 5-loop vertex graphs without lepton loops (Table 1), batched form: one
 persistent fused launch per round (Philox -> sector PDF -> graph polynomials
--> forest-formula integrand in FP64 with a running error bound -> f/p ->
-compensated per-tile sums), flagged points recomputed in double-double,
-deterministic reduction, all rounds of a step replayed from one hipGraph.
-A step is one pass over a batch of `--samples` points split evenly over the
-73 graphs (each step uses fresh sample indices of the same Philox stream).
+-> forest-formula integrand in FP64 with a probabilistic round-off estimate ->
+f/p -> compensated per-tile sums), the points whose round-off matters
+recomputed in double-double, deterministic reduction; a round is replayed from
+two captured hipGraphs.  A step is one pass over a batch of `--samples` points
+split evenly over the 73 graphs (each step uses fresh sample indices of the
+same Philox stream).  Tile and grid are autotuned before the timed steps.
 
-Prints one JSON line (see README of the build for the field meanings).
+Prints one JSON line: metric, value (evals/s), ms_per_step, the roofline of
+the fused kernel (FP64 flops of the integrand / its HIP-event time, against
+the FP64 vector peak; traffic from the committed counter record while the
+kernel is unchanged), the oracle timed on one host core, and the plain
+per-graph FP64 path timed on the same GPU.
 """
 import argparse
 import json

@@ -537,8 +537,9 @@ QA_HD double kcoef(int n, int K) {
 // homogeneous of degree -M).  f is linear in the coefficient table of the
 // last (whole-graph) piece of each term: with nslices > 1 only the share
 // `slice` of those tables' blocks is summed, and the nslices partial results
-// add up to f (the double-double pass splits a point over several waves).  Returns f; for EB the magnitude carries the
-// rounding-error scale; cond_out = worst conditioning of the graph
+// add up to f (the double-double pass splits a point over several waves).
+// Returns f (for EB with its magnitude, for ER with its rounding-error
+// variance estimate); cond_out = worst conditioning of the graph
 // polynomials seen (loop-matrix pivot ratio, cancellation ratios of flows and
 // contraction coefficients), which bounds their relative error in units of
 // the double-double round-off.
