@@ -435,7 +435,7 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
                     uint64_t hoff = P.alloc(sizeof(DevBlock) * std::max<size_t>(1, tb.blocks.size()), 64);
                     size_t ncoef = 0;
                     for (auto& b : tb.blocks) ncoef += b.coef.size();
-                    uint64_t coff = P.alloc(8 * std::max<size_t>(1, ncoef), 256);
+                    uint64_t coff = P.alloc(sizeof(qa_coef) * std::max<size_t>(1, ncoef), 256);
                     DevTable dtb{};
                     dtb.nblocks = (int)tb.blocks.size();
                     for (int k = 0, bi = 0; k <= QA_MAXN; ++k) {
@@ -465,7 +465,11 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
                         std::memcpy(db.aidx, b.aidx, QA_MAXR);
                         std::memcpy(db.cidx, b.cidx, QA_MAXR);
                         std::memcpy(P.buf.data() + hoff + bi * sizeof(DevBlock), &db, sizeof db);
-                        std::memcpy(P.buf.data() + coff + 8 * c, b.coef.data(), 8 * b.coef.size());
+                        for (size_t j = 0; j < b.coef.size(); ++j) {
+                            const qa_coef v = (qa_coef)b.coef[j];
+                            if ((double)v != b.coef[j]) throw std::runtime_error("coefficient not exact in the table format");
+                            std::memcpy(P.buf.data() + coff + sizeof(qa_coef) * (c + j), &v, sizeof v);
+                        }
                         c += b.coef.size();
                     }
                 }

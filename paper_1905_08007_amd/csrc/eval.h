@@ -265,15 +265,18 @@ template <int J> QA_HD constexpr int amap(int i) { return i + (i >= J ? 1 : 0); 
 // With Abs the leaves are |c[s]| (used with squared slot values for the
 // rounding-error estimate).
 template <class T, int R, int J, bool Abs = false> struct Fold {
-    QA_HD static T run(const QA_RO double* c, const T* A) {
+    QA_HD static T run(const QA_RO qa_coef* c, const T* A) {
         return Fold<T, R - 1, J, Abs>::run(c, A) + A[amap<J>(R - 1)] * Fold<T, R - 1, J, Abs>::run(c + (1 << (R - 1)), A);
     }
 };
 template <class T, int J, bool Abs> struct Fold<T, 0, J, Abs> {
-    QA_HD static T run(const QA_RO double* c, const T*) { return from_d<T>(Abs ? fabs(c[0]) : c[0]); }
+    QA_HD static T run(const QA_RO qa_coef* c, const T*) {
+        const double v = (double)c[0];
+        return from_d<T>(Abs ? fabs(v) : v);
+    }
 };
 
-template <class T, int J, bool Abs = false> QA_HD T fold(const QA_RO double* c, const T* A, int r) {
+template <class T, int J, bool Abs = false> QA_HD T fold(const QA_RO qa_coef* c, const T* A, int r) {
     switch (r) {
         case 0: return Fold<T, 0, J, Abs>::run(c, A);
         case 1: return Fold<T, 1, J, Abs>::run(c, A);
@@ -302,7 +305,7 @@ template <class T, int J, bool Abs = false> QA_HD T fold(const QA_RO double* c, 
 
 // sum over the free slot j carrying the q-derivative: C_j * fold(others)
 template <class T, class S, int J> struct QTerms {
-    QA_HD static void run(T& s, const QA_RO double* c, const T* A, int r, VV<S> vars, const BH& b) {
+    QA_HD static void run(T& s, const QA_RO qa_coef* c, const T* A, int r, VV<S> vars, const BH& b) {
         if (J >= r) return;
         const int half = 1 << (r - 1);
         s = s + lift_to<T>(vars.ac(b.cidx(J))) * fold<T, J>(c + (1 << r) + J * half, A, r - 1);
@@ -310,12 +313,12 @@ template <class T, class S, int J> struct QTerms {
     }
 };
 template <class T, class S> struct QTerms<T, S, QA_MAXR> {
-    QA_HD static void run(T&, const QA_RO double*, const T*, int, VV<S>, const BH&) {}
+    QA_HD static void run(T&, const QA_RO qa_coef*, const T*, int, VV<S>, const BH&) {}
 };
 
 // one block: w * (Gamma_0 fold + Gamma_1 folds)
 template <class T, class S>
-QA_HD T eval_block(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
+QA_HD T eval_block(const BH& b, const QA_RO qa_coef* c, VV<S> vars, bool has_q) {
     const int k = b.k(), r = b.r();
     T w = from_d<T>(1.0);
 #pragma unroll
@@ -333,17 +336,17 @@ QA_HD T eval_block(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
 // statically sized block (R free slots, R <= QA_STATIC_R): fully unrolled folds
 #define QA_STATIC_R 6
 template <class T, class S, int R, int J> struct QStatic {
-    QA_HD static void run(T& s, const QA_RO double* c, const T* A, VV<S> vars, const BH& b) {
+    QA_HD static void run(T& s, const QA_RO qa_coef* c, const T* A, VV<S> vars, const BH& b) {
         s = s + lift_to<T>(vars.ac(b.cidx(J))) * Fold<T, R - 1, J>::run(c + (1 << R) + J * (1 << (R - 1)), A);
         QStatic<T, S, R, J + 1>::run(s, c, A, vars, b);
     }
 };
 template <class T, class S, int R> struct QStatic<T, S, R, R> {
-    QA_HD static void run(T&, const QA_RO double*, const T*, VV<S>, const BH&) {}
+    QA_HD static void run(T&, const QA_RO qa_coef*, const T*, VV<S>, const BH&) {}
 };
 
 template <class T, class S, int R>
-QA_HD T block_static(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
+QA_HD T block_static(const BH& b, const QA_RO qa_coef* c, VV<S> vars, bool has_q) {
     const int k = b.k();
     T w = from_d<T>(1.0);
 #pragma unroll
@@ -360,10 +363,10 @@ QA_HD T block_static(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q)
 
 // sum over the free slot j carrying the q-derivative, value and square folds
 template <class S, int J> struct QTermsQ {
-    QA_HD static void run(double& s, double& sq, const QA_RO double* c, const double* A, const double* A2, int r, VV<S> vars,
+    QA_HD static void run(double& s, double& sq, const QA_RO qa_coef* c, const double* A, const double* A2, int r, VV<S> vars,
                           const BH& b) {
         if (J >= r) return;
-        const QA_RO double* cc = c + (1 << r) + J * (1 << (r - 1));
+        const QA_RO qa_coef* cc = c + (1 << r) + J * (1 << (r - 1));
         const double cj = vars.ac(b.cidx(J));
         s = s + cj * fold<double, J>(cc, A, r - 1);
         sq = sq + (cj * cj) * fold<double, J, true>(cc, A2, r - 1);
@@ -371,14 +374,14 @@ template <class S, int J> struct QTermsQ {
     }
 };
 template <class S> struct QTermsQ<S, QA_MAXR> {
-    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, int, VV<S>, const BH&) {}
+    QA_HD static void run(double&, double&, const QA_RO qa_coef*, const double*, const double*, int, VV<S>, const BH&) {}
 };
 
 // Block in EQ: the value, and q = 2^cexp * w^2 * sum_s |c_s| m_s^2 >= the sum
 // of squares of the block's monomials (m_s: product of the slot values of s;
 // 2^cexp >= max |c|).  Both folds share the coefficient loads.
 template <class S>
-QA_HD EQ eval_block_q(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
+QA_HD EQ eval_block_q(const BH& b, const QA_RO qa_coef* c, VV<S> vars, bool has_q) {
     const int k = b.k(), r = b.r();
     double w = 1.0;
 #pragma unroll
@@ -398,21 +401,21 @@ QA_HD EQ eval_block_q(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q
 }
 
 template <class S, int R, int J> struct QStaticQ {
-    QA_HD static void run(double& s, double& sq, const QA_RO double* c, const double* A, const double* A2, VV<S> vars,
+    QA_HD static void run(double& s, double& sq, const QA_RO qa_coef* c, const double* A, const double* A2, VV<S> vars,
                           const BH& b) {
         const double cj = vars.ac(b.cidx(J));
-        const QA_RO double* cc = c + (1 << R) + J * (1 << (R - 1));
+        const QA_RO qa_coef* cc = c + (1 << R) + J * (1 << (R - 1));
         s = s + cj * Fold<double, R - 1, J>::run(cc, A);
         sq = sq + (cj * cj) * Fold<double, R - 1, J, true>::run(cc, A2);
         QStaticQ<S, R, J + 1>::run(s, sq, c, A, A2, vars, b);
     }
 };
 template <class S, int R> struct QStaticQ<S, R, R> {
-    QA_HD static void run(double&, double&, const QA_RO double*, const double*, const double*, VV<S>, const BH&) {}
+    QA_HD static void run(double&, double&, const QA_RO qa_coef*, const double*, const double*, VV<S>, const BH&) {}
 };
 
 template <class S, int R>
-QA_HD EQ block_static_q(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
+QA_HD EQ block_static_q(const BH& b, const QA_RO qa_coef* c, VV<S> vars, bool has_q) {
     const int k = b.k();
     double w = 1.0;
 #pragma unroll
@@ -431,7 +434,7 @@ QA_HD EQ block_static_q(const BH& b, const QA_RO double* c, VV<S> vars, bool has
     return EQ{w * s, ldexp(w * w * sq, b.cexp())};
 }
 template <class T, class S, int R>
-QA_HD T block_any(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
+QA_HD T block_any(const BH& b, const QA_RO qa_coef* c, VV<S> vars, bool has_q) {
     if constexpr (std::is_same<T, EQ>::value) return block_static_q<S, R>(b, c, vars, has_q);
     else return block_static<T, S, R>(b, c, vars, has_q);
 }
@@ -441,7 +444,7 @@ QA_HD T block_any(const BH& b, const QA_RO double* c, VV<S> vars, bool has_q) {
 // (k + R lifted geometry values, the R-level fold, the k-pair product, the
 // final product), which acc_add uses for the ER estimate.
 template <class T, class S, int R, class AT>
-QA_HD void group_static(const QA_RO DevBlock* blocks, int b0, int b1, const QA_RO double* coefs, VV<S> vars, bool hq, AT& acc) {
+QA_HD void group_static(const QA_RO DevBlock* blocks, int b0, int b1, const QA_RO qa_coef* coefs, VV<S> vars, bool hq, AT& acc) {
     int bi = b0;
     if (bi + 1 < b1) {
         // software pipeline: the next pair's headers are loaded (clamped to the
@@ -478,7 +481,7 @@ QA_HD void eval_table(const QA_RO uint8_t* img, const QA_RO DevTable& tb, VV<S> 
     using AT = typename Acc<T>::type;
     using BT = typename BlockOf<T>::type;
     const QA_RO DevBlock* blocks = reinterpret_cast<const QA_RO DevBlock*>(img + tb.hdr_off);
-    const QA_RO double* coefs = reinterpret_cast<const QA_RO double*>(img + tb.coef_off);
+    const QA_RO qa_coef* coefs = reinterpret_cast<const QA_RO qa_coef*>(img + tb.coef_off);
     const bool hq = tb.has_q != 0;
 #pragma unroll
     for (int k = 0; k < QA_MAXN; ++k) {

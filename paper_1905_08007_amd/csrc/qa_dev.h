@@ -55,6 +55,11 @@ struct DevPiece {
     uint64_t tab_off;                      // DevTable[ntab]
 };
 
+// Coefficient tables hold integers (numerators over the table's common
+// denominator) of at most 24 bits, so float stores them exactly and halves
+// the scalar-load stream of the evaluators; the packer checks exactness.
+typedef float qa_coef;
+
 struct DevTable {
     int32_t nblocks;
     int32_t has_q;                         // Gamma_1 part present (A projector)
@@ -62,12 +67,12 @@ struct DevTable {
     int32_t pad;
     double denom;                          // common denominator of the integer coefficients
     uint64_t hdr_off;                      // DevBlock[nblocks], sorted by k
-    uint64_t coef_off;                     // double coefficients, blocks back to back
+    uint64_t coef_off;                     // qa_coef coefficients, blocks back to back
 };
 
 struct DevBlock {
     uint8_t k, r, cexp, pad1;              // cexp: 2^cexp >= max |coefficient| of the block
-    uint32_t coef;                         // offset (in doubles) from the table's coef_off
+    uint32_t coef;                         // offset (in coefficients) from the table's coef_off
     uint8_t bidx[QA_MAXK];                 // variable indices of the k pair factors
     uint8_t aidx[QA_MAXR];                 // variable indices of A for the r free slots
     uint8_t cidx[QA_MAXR];                 // variable indices of C for the r free slots
