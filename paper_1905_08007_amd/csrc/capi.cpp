@@ -463,7 +463,9 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
                         db.cexp = (uint8_t)ce;
                         std::memcpy(db.bidx, b.bidx, QA_MAXK);
                         std::memcpy(db.aidx, b.aidx, QA_MAXR);
-                        std::memcpy(db.cidx, b.cidx, QA_MAXR);
+                        for (int i = 0; i < QA_MAXR; ++i)
+                            if (i < b.r && b.cidx[i] != b.aidx[i] + (QA_VAR_C - QA_VAR_A))
+                                throw std::runtime_error("free slot with A and C of different lines");
                         std::memcpy(P.buf.data() + hoff + bi * sizeof(DevBlock), &db, sizeof db);
                         for (size_t j = 0; j < b.coef.size(); ++j) {
                             const qa_coef v = (qa_coef)b.coef[j];

@@ -224,7 +224,7 @@ QA_HD void geometry(const QA_RO DevPiece& pc, CLV<double> z, VV<S> vars, DD& U, 
 }
 
 // ---------------------------------------------------------------------------
-// A block header held in scalar registers: the 40-byte record is read as ten
+// A block header held in scalar registers: the 32-byte record is read as eight
 // wave-uniform words and its byte fields are extracted with scalar shifts
 // (a per-lane byte load would stall each block on vector-memory latency).
 QA_HD uint32_t uni(uint32_t x) {
@@ -235,7 +235,7 @@ QA_HD uint32_t uni(uint32_t x) {
 #endif
 }
 struct BH {
-    uint32_t w[10];
+    uint32_t w[8];
     QA_HD int byte(int o) const { return (int)((w[o >> 2] >> (8 * (o & 3))) & 0xffu); }
     QA_HD int k() const { return byte(0); }
     QA_HD int r() const { return byte(1); }
@@ -243,16 +243,16 @@ struct BH {
     QA_HD uint32_t coef() const { return w[1]; }
     QA_HD int bidx(int q) const { return byte(8 + q); }
     QA_HD int aidx(int i) const { return byte(13 + i); }
-    QA_HD int cidx(int i) const { return byte(25 + i); }
+    QA_HD int cidx(int i) const { return byte(13 + i) + (QA_VAR_C - QA_VAR_A); }
 };
-static_assert(sizeof(DevBlock) == 40 && offsetof(DevBlock, coef) == 4 && offsetof(DevBlock, bidx) == 8 &&
-                  offsetof(DevBlock, aidx) == 13 && offsetof(DevBlock, cidx) == 25,
+static_assert(sizeof(DevBlock) == 32 && offsetof(DevBlock, coef) == 4 && offsetof(DevBlock, bidx) == 8 &&
+                  offsetof(DevBlock, aidx) == 13,
               "block header layout");
 QA_HD BH load_bh(const QA_RO DevBlock& b) {
     const QA_RO uint32_t* p = reinterpret_cast<const QA_RO uint32_t*>(&b);
     BH h;
 #pragma unroll
-    for (int i = 0; i < 10; ++i) h.w[i] = uni(p[i]);
+    for (int i = 0; i < 8; ++i) h.w[i] = uni(p[i]);
     return h;
 }
 

@@ -74,7 +74,7 @@ struct DevBlock {
     uint8_t k, r, cexp, pad1;              // cexp: 2^cexp >= max |coefficient| of the block
     uint32_t coef;                         // offset (in coefficients) from the table's coef_off
     uint8_t bidx[QA_MAXK];                 // variable indices of the k pair factors
-    uint8_t aidx[QA_MAXR];                 // variable indices of A for the r free slots
-    uint8_t cidx[QA_MAXR];                 // variable indices of C for the r free slots
-    uint8_t pad2[3];
+    uint8_t aidx[QA_MAXR];                 // variable indices of A for the r free slots; the
+                                           // slot's C is at aidx + (QA_VAR_C - QA_VAR_A)
+    uint8_t pad2[7];                       // 32 bytes: one scalar load
 };
