@@ -451,10 +451,16 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
                     dtb.coef_off = coff;
                     std::memcpy(P.buf.data() + taboff + k * sizeof(DevTable), &dtb, sizeof dtb);
                     size_t c = 0;
+                    // identical coefficient arrays within a table are stored once (a
+                    // repeat then hits the scalar cache instead of streaming again)
+                    std::map<std::vector<double>, uint32_t> seen;
                     for (size_t bi = 0; bi < tb.blocks.size(); ++bi) {
                         const Block& b = tb.blocks[bi];
                         DevBlock db{};
                         db.k = (uint8_t)b.k; db.r = (uint8_t)b.r; db.coef = (uint32_t)c;
+                        auto ins = seen.emplace(b.coef, (uint32_t)c);
+                        const bool repeat = !ins.second;
+                        if (repeat) db.coef = ins.first->second;
                         double cmax = 0.0;
                         for (double x : b.coef) cmax = std::max(cmax, std::fabs(x));
                         int ce = 0;
@@ -467,6 +473,7 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
                             if (i < b.r && b.cidx[i] != b.aidx[i] + (QA_VAR_C - QA_VAR_A))
                                 throw std::runtime_error("free slot with A and C of different lines");
                         std::memcpy(P.buf.data() + hoff + bi * sizeof(DevBlock), &db, sizeof db);
+                        if (repeat) continue;
                         for (size_t j = 0; j < b.coef.size(); ++j) {
                             const qa_coef v = (qa_coef)b.coef[j];
                             if ((double)v != b.coef[j]) throw std::runtime_error("coefficient not exact in the table format");
