@@ -361,6 +361,57 @@ QA_HD T block_static(const BH& b, const QA_RO qa_coef* c, VV<S> vars, bool has_q
     return w * s;
 }
 
+// The value fold (leaves c) and the square fold (leaves |c|, slot values
+// squared) in one pass, so that each coefficient is converted once and feeds
+// both (|.| is a free source modifier of the FMA).
+template <int R, int J> struct Fold2 {
+    QA_HD static void run(const QA_RO qa_coef* c, const double* A, const double* A2, double& v, double& q) {
+        double v0, q0, v1, q1;
+        Fold2<R - 1, J>::run(c, A, A2, v0, q0);
+        Fold2<R - 1, J>::run(c + (1 << (R - 1)), A, A2, v1, q1);
+        v = v0 + A[amap<J>(R - 1)] * v1;
+        q = q0 + A2[amap<J>(R - 1)] * q1;
+    }
+};
+template <int J> struct Fold2<0, J> {
+    QA_HD static void run(const QA_RO qa_coef* c, const double*, const double*, double& v, double& q) {
+        const double x = (double)c[0];
+        v = x;
+        q = fabs(x);
+    }
+};
+template <int J> QA_HD void fold2(const QA_RO qa_coef* c, const double* A, const double* A2, int r, double& v, double& q) {
+    switch (r) {
+        case 0: Fold2<0, J>::run(c, A, A2, v, q); return;
+        case 1: Fold2<1, J>::run(c, A, A2, v, q); return;
+        case 2: Fold2<2, J>::run(c, A, A2, v, q); return;
+        case 3: Fold2<3, J>::run(c, A, A2, v, q); return;
+        case 4: Fold2<4, J>::run(c, A, A2, v, q); return;
+        default: break;
+    }
+    // 16-coefficient leaves combined by a carry chain over the high bits
+    double av[QA_MAXR - 4], aq[QA_MAXR - 4];
+    const int nleaves = 1 << (r - 4);
+    for (int leaf = 0; leaf < nleaves; ++leaf) {
+        Fold2<4, J>::run(c + 16 * leaf, A, A2, v, q);
+        int b = leaf;
+        bool stored = false;
+#pragma unroll
+        for (int l = 0; l < QA_MAXR - 4; ++l) {
+            if (stored || 4 + l >= r) break;
+            if ((b & 1) == 0) {
+                av[l] = v;
+                aq[l] = q;
+                stored = true;
+            } else {
+                v = av[l] + A[amap<J>(4 + l)] * v;
+                q = aq[l] + A2[amap<J>(4 + l)] * q;
+                b >>= 1;
+            }
+        }
+    }
+}
+
 // sum over the free slot j carrying the q-derivative, value and square folds
 template <class S, int J> struct QTermsQ {
     QA_HD static void run(double& s, double& sq, const QA_RO qa_coef* c, const double* A, const double* A2, int r, VV<S> vars,
@@ -368,8 +419,10 @@ template <class S, int J> struct QTermsQ {
         if (J >= r) return;
         const QA_RO qa_coef* cc = c + (1 << r) + J * (1 << (r - 1));
         const double cj = vars.ac(b.cidx(J));
-        s = s + cj * fold<double, J>(cc, A, r - 1);
-        sq = sq + (cj * cj) * fold<double, J, true>(cc, A2, r - 1);
+        double fv, fq;
+        fold2<J>(cc, A, A2, r - 1, fv, fq);
+        s = s + cj * fv;
+        sq = sq + (cj * cj) * fq;
         QTermsQ<S, J + 1>::run(s, sq, c, A, A2, r, vars, b);
     }
 };
@@ -394,8 +447,8 @@ QA_HD EQ eval_block_q(const BH& b, const QA_RO qa_coef* c, VV<S> vars, bool has_
         A2[i] = A[i] * A[i];
     }
     A[QA_MAXR] = A2[QA_MAXR] = 0.0;
-    double s = fold<double, QA_MAXR>(c, A, r);
-    double sq = fold<double, QA_MAXR, true>(c, A2, r);
+    double s, sq;
+    fold2<QA_MAXR>(c, A, A2, r, s, sq);
     if (has_q) QTermsQ<S, 0>::run(s, sq, c, A, A2, r, vars, b);
     return EQ{w * s, ldexp(w * w * sq, b.cexp())};
 }
@@ -405,8 +458,10 @@ template <class S, int R, int J> struct QStaticQ {
                           const BH& b) {
         const double cj = vars.ac(b.cidx(J));
         const QA_RO qa_coef* cc = c + (1 << R) + J * (1 << (R - 1));
-        s = s + cj * Fold<double, R - 1, J>::run(cc, A);
-        sq = sq + (cj * cj) * Fold<double, R - 1, J, true>::run(cc, A2);
+        double fv, fq;
+        Fold2<R - 1, J>::run(cc, A, A2, fv, fq);
+        s = s + cj * fv;
+        sq = sq + (cj * cj) * fq;
         QStaticQ<S, R, J + 1>::run(s, sq, c, A, A2, vars, b);
     }
 };
@@ -428,8 +483,8 @@ QA_HD EQ block_static_q(const BH& b, const QA_RO qa_coef* c, VV<S> vars, bool ha
         A2[i] = A[i] * A[i];
     }
     A[R] = A2[R] = 0.0;
-    double s = Fold<double, R, QA_MAXR>::run(c, A);
-    double sq = Fold<double, R, QA_MAXR, true>::run(c, A2);
+    double s, sq;
+    Fold2<R, QA_MAXR>::run(c, A, A2, s, sq);
     if (has_q) QStaticQ<S, R, 0>::run(s, sq, c, A, A2, vars, b);
     return EQ{w * s, ldexp(w * w * sq, b.cexp())};
 }
