@@ -14,6 +14,8 @@
  *     inside kernels surface at the next synchronising call.
  *   - handles (qa_set*, qa_pdf*) are immutable after creation and may be
  *     shared between threads.
+ *   - seeds: the Philox key is (seed, tag), two 32-bit words; every entry
+ *     point that takes a seed rejects seed >= 2^32 with QA_EINVAL.
  */
 #ifndef QEDAMM_H
 #define QEDAMM_H
@@ -51,6 +53,22 @@ typedef struct qa_acc {
     uint64_t n_bad;       /* non-finite or underflowed points, excluded */
     uint64_t n_residual;  /* recomputed points whose double-double estimate still exceeds 1e-10 of the weight scale (kept, counted) */
 } qa_acc;
+
+/* Per-graph (or set) estimate formed from the sums (host).  Every drawn
+ * sample counts: a non-finite or underflowed point (n_bad) enters as w = 0,
+ * so N = n + n_bad.  value = mult * S1 / N; sigma = mult * sqrt((S2/N -
+ * (S1/N)^2) / (N - 1)) (section "Preliminary numerical results": per-graph
+ * Monte Carlo integrals with 1-sigma errors; A_1 of a set = sum over its
+ * graphs, Table 1).  mean and sd: mean and per-sample standard deviation of
+ * w itself (no multiplicity).  For a set total: value = sum of the graphs'
+ * values, sigma = root of the sum of their squared sigmas, counts summed,
+ * mean = value and sd = sigma * sqrt(n). */
+typedef struct qa_result {
+    double value, sigma;
+    double mean, sd;
+    uint64_t n;           /* samples (good + bad) */
+    uint64_t n_bad, n_flagged, n_residual;
+} qa_result;
 
 typedef struct qa_set qa_set;   /* graphs + forests + integrand tables (host) */
 typedef struct qa_pdf qa_pdf;   /* Deg and W tables of eq. (1) (host) */
@@ -100,6 +118,22 @@ int qa_graph_flops(const qa_set* s, uint32_t graph, double* eval_flops, double* 
  * Carlo integrals (Table 1) and does not state its budgets. */
 int qa_allocate_budgets(const qa_set* s, const qa_acc* pilot, uint64_t total, uint64_t floor, uint64_t* out);
 
+/* Results from accumulator records.  qa_results: host records (ng = the
+ * set's graph count); per_graph (host, ng records, nullable) and total (host,
+ * nullable) receive the estimates defined at qa_result.  qa_acc_read: the
+ * same from device records, copied on `stream` (the call synchronises it).
+ * QA_EINVAL if a graph has fewer than 2 samples. */
+int qa_results(const qa_set* s, const qa_acc* host_acc, qa_result* per_graph, qa_result* total);
+int qa_acc_read(const qa_set* s, const qa_acc* dev_acc, qa_result* per_graph, qa_result* total, void* stream);
+
+/* Statistical combination of independent results of the same quantity
+ * (different generator keys): inverse-variance weighting, value =
+ * sum v_i / s_i^2 / sum 1 / s_i^2, sigma = (sum 1 / s_i^2)^-1/2; counts are
+ * summed, mean = value, sd = 0.  Section "Preliminary numerical results":
+ * the two calculations (two generators) are statistically combined into
+ * eq. (2).  QA_EINVAL if any sigma is not positive and finite. */
+int qa_combine(const qa_result* runs, size_t nruns, qa_result* out);
+
 /* Deg and W tables of eq. (1) for every graph of the set.  deg == NULL: the
  * default Deg rule (parametric UV degree of the I-closure, minimised over the
  * reduced graphs of all forests, floored at 1/2).  Otherwise deg holds, for
@@ -112,6 +146,22 @@ void qa_pdf_destroy(qa_pdf* p);
 int qa_pdf_tables(const qa_pdf* p, uint32_t graph, double* deg, double* w);
 /* Gradient of ln W(full) with respect to Deg(S) for graph i (2^(3n) doubles). */
 int qa_pdf_dlogw(const qa_pdf* p, uint32_t graph, double* out);
+
+/* A copy of base in which graph `graph` takes the Deg table deg (host,
+ * 2^(3n) doubles, entries 0 and full ignored, the others > 0 and finite);
+ * its W table is rebuilt.  The other graphs keep base's tables. */
+int qa_pdf_with(const qa_pdf* base, uint32_t graph, const double* deg, qa_pdf** out);
+
+/* One pilot step on graph `graph`'s exponents (the benchmark spec's differentiation
+ * form; production stays nonadaptive with the frozen result).  The exponents
+ * move by one shift per set size: theta_c = -step * g_c / max_c |g_c| with
+ * g_c = sum over |S| = c of grad[S] (grad: host, 2^(3n) doubles, the
+ * gradient d E[w^2] / d Deg(S) from qa_variance_gradient), c = 1 .. 3n-1,
+ * and Deg'(S) = max(floor, Deg(S) + theta_|S|).  theta (host, 3n doubles,
+ * nullable) receives the applied shifts (theta[0] unused).  *out: a new pdf
+ * (base unchanged).  QA_EINVAL if floor <= 0 or grad is not finite. */
+int qa_pdf_tune(const qa_pdf* base, uint32_t graph, const double* grad, double step, double floor, qa_pdf** out,
+                double* theta);
 
 /* Size of the device image holding the set's tables and the pdf tables. */
 int qa_device_bytes(const qa_set* s, const qa_pdf* p, size_t* bytes);
@@ -138,7 +188,9 @@ int qa_sample_pdf(const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, 
  * magnitude pass runs first to form it).  All include the conditioning of the
  * graph polynomials (computed in double-double in every mode).  err and flag
  * may be NULL for QA_FP64.  Units: (alpha/pi)^n.  Precision control: the
- * round-off control of Sec. 2 (interval arithmetic of several precisions). */
+ * paper removes the round-off of the numerical subtraction with interval
+ * arithmetic of several precisions (section "Preliminary numerical
+ * results"); here an FP64 bound or estimate and a double-double recompute. */
 int qa_eval_integrand(const void* dev, uint32_t graph, const double* z, uint64_t count, int mode,
                       double* f, double* err, uint8_t* flag, void* stream);
 
@@ -190,6 +242,17 @@ int qa_autotune(const qa_set* s, const void* dev, const uint64_t* budgets, uint6
  * w_i^2.  d Var / d Deg(S) = grad[S]/N + (w2sum/N) dlnW/dDeg(S). */
 int qa_variance_grad(const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, uint64_t first,
                      uint64_t count, double* grad, double* w2sum, void* stream);
+
+/* The full pilot gradient of graph `graph`: runs qa_variance_grad on
+ * samples first..first+count-1 into work (device, 2^(3n)+1 doubles, cleared
+ * here), copies the sums back (synchronising `stream`) and forms
+ *   grad[S] = d E_p[w^2] / d Deg(S) = (1/N) sum_i w_i^2 t_l(i) [S_l(i) = S]
+ *             + E_p[w^2] d ln W(full) / d Deg(S)
+ * (host, 2^(3n) doubles) and *m2 = E_p[w^2] (nullable), with p the pdf that
+ * the image on dev was uploaded from: QA_EINVAL if p's Deg table of the
+ * graph differs from the image's. */
+int qa_variance_gradient(const qa_pdf* p, const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, uint64_t first,
+                         uint64_t count, double* work, double* grad, double* m2, void* stream);
 
 /* Debug / test hook: exact Dirac trace of a symbol string (0 = on-shell
  * p-slash with p.p = 1; L > 0 = gamma contracted with the other L). */

@@ -28,6 +28,8 @@ class QaGraph(C.Structure):
 ACC_DTYPE = np.dtype([("n", "<u8"), ("s1_hi", "<f8"), ("s1_lo", "<f8"), ("s2_hi", "<f8"),
                       ("s2_lo", "<f8"), ("n_flagged", "<u8"), ("n_bad", "<u8"), ("n_residual", "<u8")])
 ACC_BYTES = ACC_DTYPE.itemsize  # 64
+RESULT_DTYPE = np.dtype([("value", "<f8"), ("sigma", "<f8"), ("mean", "<f8"), ("sd", "<f8"), ("n", "<u8"),
+                         ("n_bad", "<u8"), ("n_flagged", "<u8"), ("n_residual", "<u8")])
 
 _lib = None
 
@@ -65,6 +67,12 @@ def lib():
         L.qa_variance_grad.argtypes = [vp, u32, u64, u32, u64, u64, vp, vp, vp]
         L.qa_graph_flops.argtypes = [vp, u32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.qa_dirac_trace.argtypes = [vp, i32, C.POINTER(C.c_double)]
+        L.qa_results.argtypes = [vp, vp, vp, vp]
+        L.qa_acc_read.argtypes = [vp, vp, vp, vp, vp]
+        L.qa_combine.argtypes = [vp, sz, vp]
+        L.qa_pdf_with.argtypes = [vp, u32, vp, C.POINTER(vp)]
+        L.qa_pdf_tune.argtypes = [vp, u32, vp, C.c_double, C.c_double, C.POINTER(vp), vp]
+        L.qa_variance_gradient.argtypes = [vp, vp, u32, u64, u32, u64, u64, vp, vp, C.POINTER(C.c_double), vp]
         _lib = L
     return _lib
 
@@ -147,8 +155,11 @@ def build_forests(graphs, nthreads=0):
 class Pdf:
     """qa_pdf handle: Deg and W tables of eq. (1)."""
 
-    def __init__(self, gset, deg=None):
+    def __init__(self, gset, deg=None, _handle=None):
         self.gset = gset
+        if _handle is not None:
+            self.h = _handle
+            return
         h = C.c_void_p()
         dptr = None
         if deg is not None:
@@ -170,6 +181,27 @@ class Pdf:
         out = np.zeros(1 << M)
         _check(lib().qa_pdf_dlogw(self.h, g, out.ctypes.data_as(C.c_void_p)), "qa_pdf_dlogw")
         return out
+
+    def with_graph(self, g, deg):
+        """A new Pdf equal to this one except graph g's Deg table."""
+        d = np.ascontiguousarray(deg, dtype=np.float64)
+        if d.shape != (1 << (3 * self.gset.graphs[g].loops),):
+            raise RuntimeError("deg must hold 2^M entries")
+        h = C.c_void_p()
+        _check(lib().qa_pdf_with(self.h, g, d.ctypes.data_as(C.c_void_p), C.byref(h)), "qa_pdf_with")
+        return Pdf(self.gset, _handle=h)
+
+    def tune(self, g, grad, step, floor=0.5):
+        """One pilot step on graph g (qa_pdf_tune): returns (new Pdf, shifts per set size)."""
+        M = 3 * self.gset.graphs[g].loops
+        gr = np.ascontiguousarray(grad, dtype=np.float64)
+        if gr.shape != (1 << M,):
+            raise RuntimeError("grad must hold 2^M entries")
+        th = np.zeros(M)
+        h = C.c_void_p()
+        _check(lib().qa_pdf_tune(self.h, g, gr.ctypes.data_as(C.c_void_p), step, floor, C.byref(h),
+                                 th.ctypes.data_as(C.c_void_p)), "qa_pdf_tune")
+        return Pdf(self.gset, _handle=h), th
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -248,17 +280,40 @@ def read_acc(acc):
     return np.frombuffer(acc.cpu().numpy().tobytes(), dtype=ACC_DTYPE)
 
 
-def estimates(acc_np, mults):
-    """(value, sigma) per graph: mult * S1/N and mult * sqrt((S2/N - (S1/N)^2)/(N-1))."""
-    out = []
-    for a, mu in zip(acc_np, mults):
-        n = int(a["n"])
-        s1 = float(a["s1_hi"]) + float(a["s1_lo"])
-        s2 = float(a["s2_hi"]) + float(a["s2_lo"])
-        mean = s1 / n
-        var = (s2 / n - mean * mean) / (n - 1)
-        out.append((mu * mean, mu * float(np.sqrt(max(var, 0.0)))))
-    return out
+def results(gset, acc_np):
+    """Per-graph and set results (qa_results) from host accumulator records:
+    (numpy RESULT_DTYPE array of per-graph records, total record)."""
+    rec = np.ascontiguousarray(acc_np, dtype=ACC_DTYPE)
+    if rec.shape != (len(gset),):
+        raise RuntimeError("need one accumulator record per graph")
+    per = np.zeros(len(gset), dtype=RESULT_DTYPE)
+    tot = np.zeros(1, dtype=RESULT_DTYPE)
+    _check(lib().qa_results(gset.h, rec.ctypes.data_as(C.c_void_p), per.ctypes.data_as(C.c_void_p),
+                            tot.ctypes.data_as(C.c_void_p)), "qa_results")
+    return per, tot[0]
+
+
+def acc_read(gset, acc, stream=None):
+    """qa_acc_read: results straight from the device accumulators."""
+    per = np.zeros(len(gset), dtype=RESULT_DTYPE)
+    tot = np.zeros(1, dtype=RESULT_DTYPE)
+    _check(lib().qa_acc_read(gset.h, _ptr(acc), per.ctypes.data_as(C.c_void_p), tot.ctypes.data_as(C.c_void_p),
+                             _stream(stream)), "qa_acc_read")
+    return per, tot[0]
+
+
+def combine(runs):
+    """qa_combine: inverse-variance combination of independent result records."""
+    r = np.ascontiguousarray(np.asarray(runs, dtype=RESULT_DTYPE).reshape(-1))
+    out = np.zeros(1, dtype=RESULT_DTYPE)
+    _check(lib().qa_combine(r.ctypes.data_as(C.c_void_p), len(r), out.ctypes.data_as(C.c_void_p)), "qa_combine")
+    return out[0]
+
+
+def estimates(gset, acc_np):
+    """(value, sigma) per graph, as computed by the library (qa_results)."""
+    per, _ = results(gset, acc_np)
+    return [(float(r["value"]), float(r["sigma"])) for r in per]
 
 
 def work_bytes(gset, budgets, tile=0):
@@ -325,6 +380,20 @@ def variance_grad(img, graph, seed, tag, first, count, grad=None, w2sum=None, st
     _check(lib().qa_variance_grad(img.ptr, graph, seed, tag, first, count, _ptr(grad), _ptr(w2sum),
                                   _stream(stream)), "qa_variance_grad")
     return grad, w2sum
+
+
+def variance_gradient(pdf, img, graph, seed, tag, first, count, stream=None):
+    """qa_variance_gradient: (E[w^2], d E[w^2] / d Deg(S) for all S) of one graph
+    on samples first..first+count-1; pdf must be the one img was uploaded from."""
+    import torch
+    M = _lines(img, graph)
+    work = torch.empty((1 << M) + 1, dtype=torch.float64, device=img.buf.device)
+    grad = np.zeros(1 << M)
+    m2 = C.c_double()
+    _check(lib().qa_variance_gradient(pdf.h, img.ptr, graph, seed, tag, first, count, _ptr(work),
+                                      grad.ctypes.data_as(C.c_void_p), C.byref(m2), _stream(stream)),
+           "qa_variance_gradient")
+    return m2.value, grad
 
 
 def dirac_trace(symbols):

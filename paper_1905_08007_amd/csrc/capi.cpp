@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -157,7 +158,11 @@ extern "C" int qa_build_forests(const qa_graph* gs, size_t ng, int nthreads, qa_
     } catch (std::exception& e) { return fail(QA_ENOMEM, e.what()); }
 }
 
-extern "C" void qa_set_destroy(qa_set* s) { delete s; }
+void qa_image_forget(const void* s, const void* p);
+extern "C" void qa_set_destroy(qa_set* s) {
+    qa_image_forget(s, nullptr);
+    delete s;
+}
 
 extern "C" int qa_forests_serialize(const qa_set* s, void* buf, size_t cap, size_t* len) {
     if (!s || !len) return fail(QA_EINVAL, "NULL argument");
@@ -295,6 +300,61 @@ extern "C" int qa_allocate_budgets(const qa_set* s, const qa_acc* pilot, uint64_
     return QA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// estimates: per-graph value and sigma from the sums, set totals, and the
+// inverse-variance combination of independent runs
+
+extern "C" int qa_results(const qa_set* s, const qa_acc* acc, qa_result* per_graph, qa_result* total) {
+    if (!s || !acc) return fail(QA_EINVAL, "NULL argument");
+    const size_t ng = s->graphs.size();
+    qa_result tot{};
+    double var_tot = 0.0;
+    for (size_t g = 0; g < ng; ++g) {
+        const qa_acc& a = acc[g];
+        const uint64_t N = a.n + a.n_bad;   // a bad point is a drawn sample with w = 0
+        if (N < 2) return fail(QA_EINVAL, "graph " + std::to_string(g) + " has fewer than 2 samples");
+        const double n = (double)N, mu = (double)s->graphs[g].g.mult;
+        const double m1 = (a.s1_hi + a.s1_lo) / n, m2 = (a.s2_hi + a.s2_lo) / n;
+        const double var_w = std::max(0.0, m2 - m1 * m1);
+        qa_result r{};
+        r.mean = m1;
+        r.sd = std::sqrt(var_w * n / (n - 1.0));
+        r.value = mu * m1;
+        r.sigma = mu * std::sqrt(var_w / (n - 1.0));
+        r.n = N; r.n_bad = a.n_bad; r.n_flagged = a.n_flagged; r.n_residual = a.n_residual;
+        if (per_graph) per_graph[g] = r;
+        tot.value += r.value;
+        var_tot += r.sigma * r.sigma;
+        tot.n += r.n; tot.n_bad += r.n_bad; tot.n_flagged += r.n_flagged; tot.n_residual += r.n_residual;
+    }
+    tot.sigma = std::sqrt(var_tot);
+    tot.mean = tot.value;
+    tot.sd = tot.sigma * std::sqrt((double)tot.n);
+    if (total) *total = tot;
+    return QA_OK;
+}
+
+extern "C" int qa_combine(const qa_result* runs, size_t nruns, qa_result* out) {
+    if (!runs || !out || nruns == 0) return fail(QA_EINVAL, "NULL or empty argument");
+    double sw = 0.0, swv = 0.0;
+    qa_result r{};
+    for (size_t i = 0; i < nruns; ++i) {
+        const double s = runs[i].sigma;
+        if (!(s > 0.0) || !std::isfinite(s) || !std::isfinite(runs[i].value))
+            return fail(QA_EINVAL, "run " + std::to_string(i) + ": sigma must be positive and finite");
+        const double w = 1.0 / (s * s);
+        sw += w;
+        swv += w * runs[i].value;
+        r.n += runs[i].n; r.n_bad += runs[i].n_bad; r.n_flagged += runs[i].n_flagged; r.n_residual += runs[i].n_residual;
+    }
+    r.value = swv / sw;
+    r.sigma = 1.0 / std::sqrt(sw);
+    r.mean = r.value;
+    r.sd = 0.0;
+    *out = r;
+    return QA_OK;
+}
+
 extern "C" int qa_pdf_create(const qa_set* s, const double* deg, qa_pdf** out) {
     try {
         if (!s || !out) return fail(QA_EINVAL, "NULL argument");
@@ -319,7 +379,60 @@ extern "C" int qa_pdf_create(const qa_set* s, const double* deg, qa_pdf** out) {
     } catch (std::exception& e) { return fail(QA_ENOMEM, e.what()); }
 }
 
-extern "C" void qa_pdf_destroy(qa_pdf* p) { delete p; }
+void qa_image_forget(const void* s, const void* p);
+extern "C" void qa_pdf_destroy(qa_pdf* p) {
+    qa_image_forget(nullptr, p);
+    delete p;
+}
+
+extern "C" int qa_pdf_with(const qa_pdf* base, uint32_t graph, const double* deg, qa_pdf** out) {
+    try {
+        if (!base || !deg || !out) return fail(QA_EINVAL, "NULL argument");
+        if (graph >= base->M.size()) return fail(QA_EINVAL, "bad graph index");
+        const int M = base->M[graph];
+        std::vector<double> D(deg, deg + (size_t(1) << M));
+        for (uint32_t x = 1; x + 1 < (1u << M); ++x)
+            if (!(D[x] > 0.0) || !std::isfinite(D[x])) return fail(QA_EINVAL, "Deg entries must be positive and finite");
+        D[0] = 0.0; D[(1u << M) - 1] = 0.0;
+        auto* p = new qa_pdf(*base);
+        p->w[graph] = w_table(D, M);
+        p->deg[graph] = std::move(D);
+        *out = p;
+        return QA_OK;
+    } catch (std::exception& e) { return fail(QA_ENOMEM, e.what()); }
+}
+
+// One pilot step: a shift per set size, against the size-summed gradient,
+// normalised so that the largest shift is `step`.
+extern "C" int qa_pdf_tune(const qa_pdf* base, uint32_t graph, const double* grad, double step, double floor,
+                           qa_pdf** out, double* theta) {
+    if (!base || !grad || !out) return fail(QA_EINVAL, "NULL argument");
+    if (graph >= base->M.size()) return fail(QA_EINVAL, "bad graph index");
+    if (!(floor > 0.0) || !std::isfinite(step)) return fail(QA_EINVAL, "floor must be positive, step finite");
+    const int M = base->M[graph];
+    const uint32_t full = (1u << M) - 1;
+    std::vector<double> gc(M, 0.0);
+    for (uint32_t S = 1; S < full; ++S) {
+        if (!std::isfinite(grad[S])) return fail(QA_EINVAL, "gradient is not finite");
+        gc[__builtin_popcount(S)] += grad[S];
+    }
+    double gmax = 0.0;
+    for (int c = 1; c < M; ++c) gmax = std::max(gmax, std::fabs(gc[c]));
+    std::vector<double> th(M, 0.0);
+    if (gmax > 0.0)
+        for (int c = 1; c < M; ++c) th[c] = -step * gc[c] / gmax;
+    std::vector<double> D = base->deg[graph];
+    for (uint32_t S = 1; S < full; ++S) D[S] = std::max(floor, D[S] + th[__builtin_popcount(S)]);
+    if (theta) for (int c = 0; c < M; ++c) theta[c] = th[c];
+    return qa_pdf_with(base, graph, D.data(), out);
+}
+
+// helpers for the device-side entry points (kernels.hip)
+const std::vector<double>* qa_pdf_deg(const qa_pdf* p, uint32_t graph) {
+    return (p && graph < p->M.size()) ? &p->deg[graph] : nullptr;
+}
+std::vector<double> qa_pdf_dlogw_vec(const qa_pdf* p, uint32_t graph) { return dlogw(p->deg[graph], p->M[graph]); }
+
 
 extern "C" int qa_pdf_tables(const qa_pdf* p, uint32_t graph, double* deg, double* w) {
     if (!p || graph >= p->M.size()) return fail(QA_EINVAL, "bad graph index");
@@ -493,18 +606,20 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
     return QA_OK;
 }
 
-// image cache: the packed bytes for (set, pdf)
+// image cache: the packed bytes for (set, pdf).  Entries are dropped when
+// either handle is destroyed (a new handle may reuse the address); an image
+// that was uploaded stays alive as long as a device buffer refers to it.
 static std::mutex g_pack_mu;
-static std::map<std::pair<const void*, const void*>, std::vector<uint8_t>> g_images;
+static std::map<std::pair<const void*, const void*>, std::shared_ptr<const std::vector<uint8_t>>> g_images;
 
-const std::vector<uint8_t>* qa_image(const qa_set* s, const qa_pdf* p) {
+std::shared_ptr<const std::vector<uint8_t>> qa_image(const qa_set* s, const qa_pdf* p) {
     std::lock_guard<std::mutex> l(g_pack_mu);
     auto key = std::make_pair((const void*)s, (const void*)p);
     auto it = g_images.find(key);
-    if (it != g_images.end()) return &it->second;
-    std::vector<uint8_t> img;
-    if (pack(s, p, img) != QA_OK) return nullptr;
-    return &(g_images[key] = std::move(img));
+    if (it != g_images.end()) return it->second;
+    auto img = std::make_shared<std::vector<uint8_t>>();
+    if (pack(s, p, *img) != QA_OK) return nullptr;
+    return g_images[key] = img;
 }
 
 void qa_image_forget(const void* s, const void* p) {
@@ -517,7 +632,7 @@ void qa_image_forget(const void* s, const void* p) {
 extern "C" int qa_device_bytes(const qa_set* s, const qa_pdf* p, size_t* bytes) {
     try {
         if (!bytes) return fail(QA_EINVAL, "NULL bytes");
-        auto* img = qa_image(s, p);
+        auto img = qa_image(s, p);
         if (!img) return QA_EINVAL;
         *bytes = img->size();
         return QA_OK;

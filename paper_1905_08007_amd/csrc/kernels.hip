@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -9,7 +10,7 @@
 #include "eval.h"
 #include "host.h"
 
-const std::vector<uint8_t>* qa_image(const qa_set* s, const qa_pdf* p);
+std::shared_ptr<const std::vector<uint8_t>> qa_image(const qa_set* s, const qa_pdf* p);
 int qa_fail(int code, const std::string& msg);
 size_t qa_set_size(const qa_set* s);
 const qa::GraphTables& qa_graph_tables(const qa_set* s, size_t i);
@@ -848,16 +849,16 @@ static const DevGraph* host_graph(const std::vector<uint8_t>& img, uint32_t g) {
 #include <map>
 #include <mutex>
 static std::mutex g_up_mu;
-static std::map<const void*, const std::vector<uint8_t>*> g_uploaded;
+static std::map<const void*, std::shared_ptr<const std::vector<uint8_t>>> g_uploaded;
 
-static const std::vector<uint8_t>* image_of(const void* dev) {
+static std::shared_ptr<const std::vector<uint8_t>> image_of(const void* dev) {
     std::lock_guard<std::mutex> l(g_up_mu);
     auto it = g_uploaded.find(dev);
     return it == g_uploaded.end() ? nullptr : it->second;
 }
 
 extern "C" int qa_upload(const qa_set* s, const qa_pdf* p, void* dev, size_t bytes, void* stream) {
-    auto* img = qa_image(s, p);
+    auto img = qa_image(s, p);
     if (!img) return QA_EINVAL;
     if (!dev || bytes < img->size()) return qa_fail(QA_ECAP, "device buffer too small");
     HIPCHK(hipMemcpyAsync(dev, img->data(), img->size(), hipMemcpyHostToDevice, (hipStream_t)stream));
@@ -869,12 +870,13 @@ extern "C" int qa_upload(const qa_set* s, const qa_pdf* p, void* dev, size_t byt
 
 extern "C" int qa_sample_pdf(const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, uint64_t first,
                              uint64_t count, double* z, double* logp, uint8_t* sector, void* stream) {
-    auto* img = image_of(dev);
+    auto img = image_of(dev);
     if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
     if (!host_graph(*img, graph)) return qa_fail(QA_EINVAL, "graph index out of range");
     if (count == 0) return QA_OK;
     if (!z || !logp) return qa_fail(QA_EINVAL, "NULL output");
     if (count > (1ull << 31)) return qa_fail(QA_EINVAL, "count too large for one call");
+    if (seed >> 32) return qa_fail(QA_EINVAL, "seed must be below 2^32 (32-bit Philox key word)");
     const uint2 key = make_uint2((uint32_t)seed, tag);
     dim3 grid((unsigned)((count + 255) / 256));
     hipLaunchKernelGGL(k_sample, grid, dim3(256), 0, (hipStream_t)stream, (const uint8_t*)dev, graph, key, first,
@@ -885,7 +887,7 @@ extern "C" int qa_sample_pdf(const void* dev, uint32_t graph, uint64_t seed, uin
 
 extern "C" int qa_eval_integrand(const void* dev, uint32_t graph, const double* z, uint64_t count, int mode, double* f,
                                  double* err, uint8_t* flag, void* stream) {
-    auto* img = image_of(dev);
+    auto img = image_of(dev);
     if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
     const DevGraph* G = host_graph(*img, graph);
     if (!G) return qa_fail(QA_EINVAL, "graph index out of range");
@@ -991,9 +993,10 @@ extern "C" int qa_work_bytes(const qa_set* s, const uint64_t* budgets, uint32_t 
 extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t first, uint64_t seed,
                             uint32_t tag, uint32_t tile, uint32_t grid, void* work, size_t work_bytes, qa_acc* acc,
                             double* fused_ms, void* stream) {
-    auto* img = image_of(dev);
+    auto img = image_of(dev);
     if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
     if (!s || !budgets || !work || !acc) return qa_fail(QA_EINVAL, "NULL argument");
+    if (seed >> 32) return qa_fail(QA_EINVAL, "seed must be below 2^32 (32-bit Philox key word)");
     const size_t ng = qa_set_size(s);
     if (reinterpret_cast<const DevHeader*>(img->data())->ngraphs != ng) return qa_fail(QA_EINVAL, "set / image mismatch");
     if (tile == 0) tile = kDefaultTile;
@@ -1128,6 +1131,7 @@ extern "C" int qa_autotune(const qa_set* s, const void* dev, const uint64_t* bud
                            uint64_t pilot, void* work, size_t work_bytes, qa_acc* acc, uint32_t* tile_out,
                            uint32_t* grid_out, double* ns_per_sample, void* stream) {
     if (!s || !dev || !budgets || !work || !acc || !tile_out || !grid_out) return qa_fail(QA_EINVAL, "NULL argument");
+    if (seed >> 32) return qa_fail(QA_EINVAL, "seed must be below 2^32 (32-bit Philox key word)");
     const size_t ng = qa_set_size(s);
     double total = 0.0;
     for (size_t g = 0; g < ng; ++g) total += (double)budgets[g];
@@ -1171,18 +1175,64 @@ extern "C" int qa_autotune(const qa_set* s, const void* dev, const uint64_t* bud
 
 extern "C" int qa_variance_grad(const void* dev, uint32_t graph, uint64_t seed, uint32_t tag, uint64_t first,
                                 uint64_t count, double* grad, double* w2sum, void* stream) {
-    auto* img = image_of(dev);
+    auto img = image_of(dev);
     if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
     const DevGraph* G = host_graph(*img, graph);
     if (!G) return qa_fail(QA_EINVAL, "graph index out of range");
     if (count == 0) return QA_OK;
     if (!grad || !w2sum) return qa_fail(QA_EINVAL, "NULL argument");
     if (count > (1ull << 31)) return qa_fail(QA_EINVAL, "count too large for one call");
+    if (seed >> 32) return qa_fail(QA_EINVAL, "seed must be below 2^32 (32-bit Philox key word)");
     const unsigned nb = (unsigned)((count + 63) / 64);
     if (int rc = lds_attr(k_vargrad, lds_bytes<double>(G->npoly, 64) + 8 * QA_MAXM * 64)) return rc;
     hipLaunchKernelGGL(k_vargrad, dim3(nb), dim3(64), lds_bytes<double>(G->npoly, 64) + 8 * QA_MAXM * 64,
                        (hipStream_t)stream, (const uint8_t*)dev, graph, make_uint2((uint32_t)seed, tag), first, count,
                        grad, w2sum);
     HIPCHK(hipGetLastError());
+    return QA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// results and the assembled pilot gradient (device copies + host arithmetic)
+
+const std::vector<double>* qa_pdf_deg(const qa_pdf* p, uint32_t graph);
+std::vector<double> qa_pdf_dlogw_vec(const qa_pdf* p, uint32_t graph);
+
+extern "C" int qa_acc_read(const qa_set* s, const qa_acc* dev_acc, qa_result* per_graph, qa_result* total,
+                           void* stream) {
+    if (!s || !dev_acc) return qa_fail(QA_EINVAL, "NULL argument");
+    std::vector<qa_acc> h(qa_set_size(s));
+    if (h.empty()) return qa_fail(QA_EINVAL, "empty set");
+    HIPCHK(hipMemcpyAsync(h.data(), dev_acc, sizeof(qa_acc) * h.size(), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    return qa_results(s, h.data(), per_graph, total);
+}
+
+extern "C" int qa_variance_gradient(const qa_pdf* p, const void* dev, uint32_t graph, uint64_t seed, uint32_t tag,
+                                    uint64_t first, uint64_t count, double* work, double* grad, double* m2,
+                                    void* stream) {
+    auto img = image_of(dev);
+    if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
+    const DevGraph* G = host_graph(*img, graph);
+    if (!G) return qa_fail(QA_EINVAL, "graph index out of range");
+    const std::vector<double>* D = qa_pdf_deg(p, graph);
+    if (!D || D->size() != (size_t(1) << G->M)) return qa_fail(QA_EINVAL, "pdf does not match the image");
+    if (std::memcmp(D->data(), img->data() + G->deg_off, 8 * D->size()) != 0)
+        return qa_fail(QA_EINVAL, "the image on dev was not uploaded from this pdf");
+    if (!work || !grad) return qa_fail(QA_EINVAL, "NULL argument");
+    if (count < 1) return qa_fail(QA_EINVAL, "count must be positive");
+    const size_t nS = size_t(1) << G->M;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemsetAsync(work, 0, 8 * (nS + 1), st));
+    if (int rc = qa_variance_grad(dev, graph, seed, tag, first, count, work, work + nS, stream)) return rc;
+    std::vector<double> h(nS + 1);
+    HIPCHK(hipMemcpyAsync(h.data(), work, 8 * (nS + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double N = (double)count, mom2 = h[nS] / N;
+    const std::vector<double> dl = qa_pdf_dlogw_vec(p, graph);
+    for (size_t S = 0; S < nS; ++S) grad[S] = h[S] / N + mom2 * dl[S];
+    grad[0] = 0.0;
+    grad[nS - 1] = 0.0;
+    if (m2) *m2 = mom2;
     return QA_OK;
 }

@@ -175,7 +175,7 @@ def _plain_integral(n, per_graph, seed, chunk=1 << 20):
             done += c
     sync()
     a = P.read_acc(acc)
-    est = P.estimates(a, [g.mult for g in gs])
+    est = P.estimates(s, a)
     return a, est
 
 
@@ -395,3 +395,63 @@ def test_autotune_picks_a_candidate_and_integrates():
         assert int(x["n"]) == int(y["n"]) and int(x["n_flagged"]) == int(y["n_flagged"])
         s1x, s1y = x["s1_hi"] + x["s1_lo"], y["s1_hi"] + y["s1_lo"]
         assert abs(s1x - s1y) <= 1e-12 * math.sqrt((y["s2_hi"] + y["s2_lo"]) * max(1, int(y["n"])))
+
+
+def test_variance_fn_backward_matches_reweighted_finite_differences():
+    """VarianceFn (torch.autograd.Function over the library's backward kernel):
+    deg.grad against central finite differences of the reweighted second
+    moment V(theta') = (1/N) sum w_i^2 p_theta(z_i) / p_theta'(z_i) on the same
+    Philox samples (its derivative at theta' = theta is the gradient exactly)."""
+    gs, s, p, img, og = setup(2)
+    gi, seed, tag, count, M = 1, 6, 1, 4096, 6
+    D0, W0 = p.tables(gi)
+    deg = torch.tensor(D0, dtype=torch.float64, requires_grad=True)
+    y = P.VarianceFn.apply(deg, (p, gi, seed, tag, 0, count))
+    y.backward()
+    g = deg.grad.numpy()
+    m2, g2 = P.variance_gradient(p, img, gi, seed, tag, 0, count)
+    assert float(y) == m2 and np.array_equal(g, g2)
+    z, lp, sec = P.sample_pdf(img, gi, seed, tag, 0, count, want_sector=True)
+    f, _, _ = P.eval_integrand(img, gi, z, P.QA_FP64)
+    sync()
+    z, lp, sec, f = z.cpu().numpy(), lp.cpu().numpy(), sec.cpu().numpy().astype(np.int64), f.cpu().numpy()
+    w2 = (f * np.exp(-lp)) ** 2
+    assert abs(w2.mean() - m2) <= 1e-12 * m2
+    full = (1 << M) - 1
+    # S_l and t_l of every sample from its sector
+    S = np.full(count, full)
+    sets, ts = [], []
+    for l in range(1, M):
+        S = S ^ (1 << sec[l - 1])
+        sets.append(S.copy())
+        ts.append(np.log(z[sec[l - 1], np.arange(count)] / z[sec[l], np.arange(count)]))
+    sets, ts = np.array(sets), np.array(ts)
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=1 << M)
+    u[0] = u[full] = 0.0
+
+    def logp(Dt, Wt):
+        return -np.log(Wt[full]) - (Dt[sets] * ts).sum(axis=0) - np.log(z).sum(axis=0)
+
+    assert np.allclose(logp(D0, W0), lp, rtol=0, atol=1e-11 * np.abs(lp).max())
+    h = 1e-5
+    V = []
+    for sg in (1, -1):
+        Dt = D0 + sg * h * u
+        Wt = p.with_graph(gi, Dt).tables(gi)[1]
+        V.append(np.mean(w2 * np.exp(lp - logp(Dt, Wt))))
+    fd = (V[0] - V[1]) / (2 * h)
+    assert abs(fd - g @ u) <= 1e-6 * np.abs(g * u).sum(), (fd, g @ u)
+
+
+def test_acc_read_and_seed_checks():
+    gs, s, p, img, og = setup(2)
+    acc = P.integrate(s, img, [5000, 300, 4000, 64], seed=9, tag=0)
+    per, tot = P.acc_read(s, acc)
+    per2, tot2 = P.results(s, P.read_acc(acc))
+    assert per.tobytes() == per2.tobytes() and tot.tobytes() == tot2.tobytes()
+    assert [int(r["n"]) for r in per] == [5000, 300, 4000, 64]
+    with pytest.raises(RuntimeError):
+        P.sample_pdf(img, 0, 1 << 32, 0, 0, 16)
+    with pytest.raises(RuntimeError):
+        P.integrate(s, img, [64] * 4, seed=1 << 33)
