@@ -12,9 +12,11 @@ same Philox stream).  Tile and grid are autotuned before the timed steps.
 
 Prints one JSON line: metric, value (evals/s), ms_per_step, the roofline of
 the fused kernel (FP64 flops of the integrand / its HIP-event time, against
-the FP64 vector peak; traffic from the committed counter record while the
-kernel is unchanged), the oracle timed on one host core, and the plain
-per-graph FP64 path timed on the same GPU.
+the FP64 vector peak, dense and with the folds priced at their nonzero
+coefficients; traffic from the committed counter record while the kernel is
+unchanged), per-graph results with a tail check, the oracle timed on the
+host's cores (after the GPU work), and the plain per-graph FP64 path timed on
+the same GPU.
 """
 import argparse
 import json
@@ -34,27 +36,55 @@ METRIC = "5-loop subtracted integrand evals/s on 1 GPU; MC σ reached per GPU-ho
 SEED = 5
 
 
-def oracle_baseline(q, seconds):
-    """CPU baseline: the oracle (test infrastructure) on one host core, for one
-    graph of class (5,0,0): sector sampling + subtracted integrand + f/p, after
-    its one-time table setup (reported separately)."""
+def _oracle_worker(gi, seconds, q):
+    """One host core: the oracle (test infrastructure) on graph gi of class
+    (5,0,0): its one-time table setup, then sector sampling + subtracted
+    integrand + f/p for `seconds`."""
     try:
         from oracle import graphs as GR, mc
-        g = GR.enumerate_graphs(5, (5, 0, 0))[1]
+        g = GR.enumerate_graphs(5, (5, 0, 0))[gi]
         t0 = time.time()
-        mc.graph_samples(g, 1, SEED, 0, 1, tag=2)        # builds the oracle's monomial tables
+        mc.graph_samples(g, gi, SEED, 0, 1, tag=2)        # builds the oracle's monomial tables
         setup = time.time() - t0
         n = 0
         t0 = time.time()
         while time.time() - t0 < seconds:
-            mc.graph_samples(g, 1, SEED, 1 + n, 4, tag=2)
-            n += 4
-        dt = time.time() - t0
-        q.put({"value": n / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-               "sample": f"{n} points of graph 1 of class (5,0,0) (x={g['x']}), sampling + f + f/p, "
-                         f"{dt:.1f} s on one core after {setup:.1f} s one-time setup"})
+            mc.graph_samples(g, gi, SEED, 1 + n, 1, tag=2)
+            n += 1
+        q.put((gi, n, time.time() - t0, setup))
     except Exception as e:  # noqa: BLE001
-        q.put({"error": repr(e)})
+        q.put((gi, -1, repr(e), 0.0))
+
+
+def oracle_baseline(seconds, cores):
+    """CPU baseline: the oracle on `cores` host cores at once, one process per
+    core, each on a different graph of class (5,0,0) spread evenly over the
+    class (so the mix of term counts follows the class), each timed for
+    `seconds` after its setup.  Rate = sum over cores of points / time."""
+    ctx = mp.get_context("spawn")
+    q = ctx.Queue()
+    graphs = sorted({round(i * 72 / max(1, cores - 1)) for i in range(cores)})
+    procs = [ctx.Process(target=_oracle_worker, args=(gi, seconds, q)) for gi in graphs]
+    for pr in procs:
+        pr.start()
+    res = [q.get(timeout=900) for _ in procs]
+    for pr in procs:
+        pr.join(timeout=60)
+    ok = [r for r in res if r[1] > 0]
+    if not ok:
+        return {"error": "oracle baseline failed: " + "; ".join(str(r[2]) for r in res)}
+    rate = sum(n / dt for _, n, dt, _ in ok)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": rate, "unit": "evals/s", "cores": len(ok), "kind": "oracle",
+            "sample": f"{sum(n for _, n, _, _ in ok)} points over {len(ok)} graphs of class (5,0,0) "
+                      f"(indices {[gi for gi, *_ in ok]}), one process per core, about {seconds:.0f} s each after "
+                      f"a one-time setup of {max(st for *_, st in ok):.0f} s; sampling + f + f/p in long double",
+            "host_cores": os.cpu_count(), "cpu_model": model}
 
 
 def measured_traffic(samples_per_launch):
@@ -78,7 +108,7 @@ def measured_traffic(samples_per_launch):
     return rec["bytes_per_sample"] * samples_per_launch
 
 
-def plain_path(P, img, graphs, per_graph, first):
+def plain_path(P, gset, img, graphs, per_graph, first):
     """The plain per-graph FP64 path on the same GPU, for comparison with the
     batched form: for each graph in turn qa_sample_pdf -> qa_eval_integrand
     (FP64) -> qa_accumulate, per_graph samples each (outside the timed region
@@ -94,15 +124,10 @@ def plain_path(P, img, graphs, per_graph, first):
         P.accumulate(f, lp, acc, g)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    a = P.read_acc(acc)
-    var = 0.0
-    for i, gr in enumerate(graphs):
-        n = float(a["n"][i])
-        m = (a["s1_hi"][i] + a["s1_lo"][i]) / n
-        v = ((a["s2_hi"][i] + a["s2_lo"][i]) / n - m * m) / (n - 1)
-        var += gr.mult ** 2 * v
-    return {"evals_per_s": per_graph * ng / dt, "sigma_per_gpu_hour": math.sqrt(var) * math.sqrt(dt / 3600.0),
-            "samples_per_graph": per_graph}
+    per, tot = P.acc_read(gset, acc)
+    return {"evals_per_s": per_graph * ng / dt, "sigma_per_gpu_hour": float(tot["sigma"]) * math.sqrt(dt / 3600.0),
+            "samples_per_graph": per_graph,
+            "per_graph_sigma_per_gpu_hour": [round(float(r["sigma"]) * math.sqrt(dt / 3600.0), 6) for r in per]}
 
 
 def main():
@@ -115,6 +140,8 @@ def main():
     ap.add_argument("--grid", type=int, default=0, help="persistent waves; 0 with --tile 0: autotuned")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-cores", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host cores (processes) of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-samples", type=int, default=1 << 16,
                     help="samples per graph of the plain per-graph FP64 comparison (0: skip)")
@@ -138,15 +165,7 @@ def main():
     budgets = np.full(ng, per, dtype=np.uint64)
     flops = [gset.flops(i) for i in range(ng)]
     eval_flops_step = float(sum(per * a for a, _ in flops))
-    all_flops_step = float(sum(per * (a + b) for a, b in flops))
-
-    q = None
-    proc = None
-    if not args.no_cpu_baseline:
-        ctx = mp.get_context("spawn")
-        q = ctx.Queue()
-        proc = ctx.Process(target=oracle_baseline, args=(q, args.cpu_seconds))
-        proc.start()
+    eval_flops_nz_step = float(sum(per * gset.flops_nonzero(i) for i in range(ng)))
 
     tuned_ns = None
     if args.tile == 0 and args.grid == 0:
@@ -172,41 +191,43 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
-    # per-graph sums over the timed steps
-    tot = np.zeros(ng, dtype=[("n", "f8"), ("s1", "f8"), ("s2", "f8"), ("flag", "f8"), ("bad", "f8"), ("res", "f8")])
-    for acc in accs:
+    # per-graph results over the timed steps (the library merges the sums and
+    # forms the estimates); tail check: each graph's per-sample sd after the
+    # first step, a quarter of the steps and all of them, and the largest
+    # share of its sum of w^2 that a single step holds (1/steps for light tails)
+    merged = np.zeros(ng, dtype=P.ACC_DTYPE)
+    marks = sorted({1, max(1, args.steps // 4), args.steps})
+    sd_at, s2_steps = {}, []
+    for k, acc in enumerate(accs, 1):
         a = P.read_acc(acc)
-        tot["n"] += a["n"]
-        tot["s1"] += a["s1_hi"] + a["s1_lo"]
-        tot["s2"] += a["s2_hi"] + a["s2_lo"]
-        tot["flag"] += a["n_flagged"]
-        tot["bad"] += a["n_bad"]
-        tot["res"] += a["n_residual"]
-    val, var = 0.0, 0.0
-    for i, g in enumerate(graphs):
-        n = tot["n"][i]
-        m = tot["s1"][i] / n
-        v = (tot["s2"][i] / n - m * m) / (n - 1)
-        val += g.mult * m
-        var += g.mult ** 2 * v
-    sigma = math.sqrt(var)
+        s2_steps.append(a["s2_hi"] + a["s2_lo"])
+        merged = P.acc_merge(merged, a)
+        if k in marks:
+            sd_at[k] = P.results(gset, merged)[0]["sd"]
+    per_res, tot = P.results(gset, merged)
+    s2_steps = np.array(s2_steps)
+    step_share = s2_steps.max(axis=0) / np.maximum(s2_steps.sum(axis=0), 1e-300)
+    val, sigma = float(tot["value"]), float(tot["sigma"])
+    per_graph = [[int(r["n"]), round(float(r["mean"]), 6), round(float(r["sigma"]), 6)] +
+                 [round(float(sd_at[k][i]), 2) for k in marks] + [round(float(step_share[i]), 3)]
+                 for i, r in enumerate(per_res)]
     samples = float(per * ng * args.steps)
     evals_s = samples / dt
     sigma_gpu_hour = sigma * math.sqrt(dt / 3600.0)
     achieved = eval_flops_step * args.steps / (fused_ms * 1e-3) / 1e12
+    achieved_nz = eval_flops_nz_step * args.steps / (fused_ms * 1e-3) / 1e12
 
     plain = None
     if args.plain_samples > 0:
-        plain = plain_path(P, img, graphs, args.plain_samples, first=step * per)
+        plain = plain_path(P, gset, img, graphs, args.plain_samples, first=step * per)
         # Both paths sample the same distribution; the per-sample variance of these
         # heavy-tailed weights is far better estimated by the batched run's N, so the
         # comparison at equal per-sample sigma is sigma_hour * sqrt(rate ratio).
         plain["sigma_per_gpu_hour_at_batched_variance"] = sigma_gpu_hour * math.sqrt(evals_s / plain["evals_per_s"])
 
     cpu = None
-    if proc is not None:
-        proc.join(timeout=600)
-        cpu = q.get() if not q.empty() else {"error": "oracle baseline did not report"}
+    if not args.no_cpu_baseline:   # after the GPU work: the oracle takes every host core it is given
+        cpu = oracle_baseline(args.cpu_seconds, args.cpu_cores)
 
     out = {
         "metric": METRIC,
@@ -234,12 +255,17 @@ def main():
             "plain_per_graph_fp64": plain,
             "class_value": val,
             "class_sigma": sigma,
-            "flagged_fraction": float(tot["flag"].sum() / max(1.0, tot["n"].sum())),
-            "bad_points": int(tot["bad"].sum()),
-            "residual_points": int(tot["res"].sum()),
+            "flagged_fraction": float(tot["n_flagged"]) / max(1.0, float(tot["n"])),
+            "bad_points": int(tot["n_bad"]),
+            "residual_points": int(tot["n_residual"]),
             "host_setup_s": setup_s,
             "fused_kernel_ms_per_step": fused_ms / args.steps,
             "eval_flops_per_sample": eval_flops_step / (per * ng),
+            "eval_flops_per_sample_nonzero": eval_flops_nz_step / (per * ng),
+            "roofline_frac_nonzero": achieved_nz / FP64_PEAK_TFLOPS,
+            "per_graph_fields": ["N", "mean w", "sigma (x mult)"] + [f"sd of w after {k} step(s)" for k in marks] +
+                                ["largest one-step share of sum w^2"],
+            "per_graph": per_graph,
         },
         "roofline": {
             "bound": "alu",

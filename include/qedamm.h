@@ -107,6 +107,12 @@ int qa_set_stats(const qa_set* s, uint64_t* nterms, uint64_t* nblocks, uint64_t*
  * sampler; an FMA counts 2.  Used for the roofline of the integrand kernel. */
 int qa_graph_flops(const qa_set* s, uint32_t graph, double* eval_flops, double* sample_flops);
 
+/* The same count with the coefficient folds priced at their nonzero
+ * coefficients only (2 per nonzero coefficient instead of the dense 2^r fold;
+ * the rest unchanged): the work a fold restricted to the nonzero monomials
+ * would do. */
+int qa_graph_flops_nonzero(const qa_set* s, uint32_t graph, double* eval_flops);
+
 /* Per-graph budgets from a pilot (host arrays; pilot = ng qa_acc records read
  * back from the device): N_g = floor + share of (total - ng*floor) in
  * proportion to mu_g sigma_g / sqrt(c_g) (sigma_g the pilot's per-sample
@@ -125,6 +131,10 @@ int qa_allocate_budgets(const qa_set* s, const qa_acc* pilot, uint64_t total, ui
  * QA_EINVAL if a graph has fewer than 2 samples. */
 int qa_results(const qa_set* s, const qa_acc* host_acc, qa_result* per_graph, qa_result* total);
 int qa_acc_read(const qa_set* s, const qa_acc* dev_acc, qa_result* per_graph, qa_result* total, void* stream);
+
+/* into[i] += from[i] for n host records: sums added as double-double,
+ * counts added (runs over disjoint sample ranges of the same streams). */
+int qa_acc_merge(qa_acc* into, const qa_acc* from, size_t n);
 
 /* Statistical combination of independent results of the same quantity
  * (different generator keys): inverse-variance weighting, value =

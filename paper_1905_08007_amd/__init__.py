@@ -73,6 +73,8 @@ def lib():
         L.qa_pdf_with.argtypes = [vp, u32, vp, C.POINTER(vp)]
         L.qa_pdf_tune.argtypes = [vp, u32, vp, C.c_double, C.c_double, C.POINTER(vp), vp]
         L.qa_variance_gradient.argtypes = [vp, vp, u32, u64, u32, u64, u64, vp, vp, C.POINTER(C.c_double), vp]
+        L.qa_acc_merge.argtypes = [vp, vp, sz]
+        L.qa_graph_flops_nonzero.argtypes = [vp, u32, C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -141,6 +143,12 @@ class GraphSet:
         a, b = C.c_double(), C.c_double()
         _check(lib().qa_graph_flops(self.h, g, C.byref(a), C.byref(b)), "qa_graph_flops")
         return a.value, b.value
+
+    def flops_nonzero(self, g):
+        """Evaluation flops of graph g with the folds priced at their nonzero coefficients."""
+        a = C.c_double()
+        _check(lib().qa_graph_flops_nonzero(self.h, g, C.byref(a)), "qa_graph_flops_nonzero")
+        return a.value
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -300,6 +308,16 @@ def acc_read(gset, acc, stream=None):
     _check(lib().qa_acc_read(gset.h, _ptr(acc), per.ctypes.data_as(C.c_void_p), tot.ctypes.data_as(C.c_void_p),
                              _stream(stream)), "qa_acc_read")
     return per, tot[0]
+
+
+def acc_merge(into, frm):
+    """qa_acc_merge: into += frm (host accumulator records, equal length); returns into."""
+    a = np.ascontiguousarray(into, dtype=ACC_DTYPE)
+    b = np.ascontiguousarray(frm, dtype=ACC_DTYPE)
+    if a.shape != b.shape:
+        raise RuntimeError("records of different lengths")
+    _check(lib().qa_acc_merge(a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), len(a)), "qa_acc_merge")
+    return a
 
 
 def combine(runs):

@@ -254,6 +254,24 @@ extern "C" int qa_graph_flops(const qa_set* s, uint32_t graph, double* eval_flop
     return QA_OK;
 }
 
+extern "C" int qa_graph_flops_nonzero(const qa_set* s, uint32_t graph, double* eval_flops) {
+    if (!s || graph >= s->graphs.size() || !eval_flops) return fail(QA_EINVAL, "bad argument");
+    double dense = 0.0;
+    if (int rc = qa_graph_flops(s, graph, &dense, nullptr)) return rc;
+    const auto& T = s->graphs[graph];
+    double fold_dense = 0.0, fold_nz = 0.0;
+    for (auto& tv : T.tabs)
+        for (auto& pv : tv)
+            for (auto& tb : pv)
+                for (auto& b : tb.blocks) {
+                    fold_dense += 2.0 * ((1 << b.r) - 1);
+                    if (tb.has_q) fold_dense += b.r * (2.0 * ((1 << (b.r > 0 ? b.r - 1 : 0)) - 1) + 2);
+                    for (double x : b.coef) fold_nz += 2.0 * (x != 0.0);
+                }
+    *eval_flops = dense - fold_dense + fold_nz;
+    return QA_OK;
+}
+
 // Budgets across graphs from a pilot (Neyman allocation: the variance of the
 // set total, sum mu_g^2 sigma_g^2 / N_g, is smallest at a fixed cost sum c_g N_g
 // when N_g is proportional to mu_g sigma_g / sqrt(c_g)); every graph gets at
@@ -331,6 +349,26 @@ extern "C" int qa_results(const qa_set* s, const qa_acc* acc, qa_result* per_gra
     tot.mean = tot.value;
     tot.sd = tot.sigma * std::sqrt((double)tot.n);
     if (total) *total = tot;
+    return QA_OK;
+}
+
+static void dd_add_into(double& hi, double& lo, double bhi, double blo) {
+    // two-sum of the high parts, then the low parts (double-double addition)
+    const double s = hi + bhi, bb = s - hi, e = (hi - (s - bb)) + (bhi - bb) + lo + blo;
+    hi = s + e;
+    lo = e - (hi - s);
+}
+
+extern "C" int qa_acc_merge(qa_acc* into, const qa_acc* from, size_t n) {
+    if (!into || !from) return fail(QA_EINVAL, "NULL argument");
+    for (size_t i = 0; i < n; ++i) {
+        dd_add_into(into[i].s1_hi, into[i].s1_lo, from[i].s1_hi, from[i].s1_lo);
+        dd_add_into(into[i].s2_hi, into[i].s2_lo, from[i].s2_hi, from[i].s2_lo);
+        into[i].n += from[i].n;
+        into[i].n_flagged += from[i].n_flagged;
+        into[i].n_bad += from[i].n_bad;
+        into[i].n_residual += from[i].n_residual;
+    }
     return QA_OK;
 }
 

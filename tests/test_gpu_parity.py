@@ -410,7 +410,9 @@ def test_variance_fn_backward_matches_reweighted_finite_differences():
     y.backward()
     g = deg.grad.numpy()
     m2, g2 = P.variance_gradient(p, img, gi, seed, tag, 0, count)
-    assert float(y) == m2 and np.array_equal(g, g2)
+    # the backward kernel scatters with atomics: sums agree to rounding, not bitwise
+    assert abs(float(y.detach()) - m2) <= 1e-13 * m2
+    assert np.allclose(g, g2, rtol=1e-12, atol=1e-14 * np.abs(g2).max())
     z, lp, sec = P.sample_pdf(img, gi, seed, tag, 0, count, want_sector=True)
     f, _, _ = P.eval_integrand(img, gi, z, P.QA_FP64)
     sync()

@@ -98,3 +98,26 @@ def test_pdf_with_and_tune():
     assert np.array_equal(Wr, PD.w_table(Dr, 6))
     with pytest.raises(RuntimeError):
         p.tune(1, grad, 0.25, floor=0.0)
+
+
+def test_acc_merge_and_nonzero_flops():
+    gs = P.enumerate_graphs(2)
+    s = P.build_forests(gs, 2)
+    rng = np.random.default_rng(4)
+    a, sa = _records(gs, rng)
+    b, sb = _records(gs, rng)
+    m = P.acc_merge(a.copy(), b)
+    per, _ = P.results(s, m)
+    for g in range(len(gs)):
+        N, S1, S2 = mc.sums(sa[g] + sb[g])
+        assert int(m[g]["n"]) == N
+        assert abs(m[g]["s1_hi"] + m[g]["s1_lo"] - S1) <= 1e-15 * sum(abs(x) for x in sa[g] + sb[g])
+        assert abs(m[g]["s2_hi"] + m[g]["s2_lo"] - S2) <= 1e-15 * S2
+        v, e = mc.estimate(N, S1, S2, gs[g].mult)
+        assert abs(per[g]["value"] - v) <= 1e-13 * max(1.0, abs(v))
+    with pytest.raises(RuntimeError):
+        P.acc_merge(a, b[:2])
+    for g in range(len(gs)):
+        dense, _ = s.flops(g)
+        nz = s.flops_nonzero(g)
+        assert 0 < nz <= dense
