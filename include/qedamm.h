@@ -233,6 +233,27 @@ int qa_integrate(const qa_set* s, const void* dev, const uint64_t* budgets, uint
                  uint32_t tag, uint32_t tile, uint32_t grid, void* work, size_t work_bytes, qa_acc* acc,
                  double* fused_ms, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops or harnesses that forbid hipMalloc): the batched form of
+ * qa_integrate with no work argument and no allocation of any kind.  Its work
+ * memory is a library-owned device array of 384 MiB per GPU, reserved when
+ * the library's code object is loaded on that GPU and held until the process
+ * ends; its address is looked up once per GPU (hipGetSymbolAddress).  The
+ * call enqueues only kernel launches on `stream` (budgets travel in kernel
+ * arguments; counters and acc are cleared by kernels; no private stream,
+ * hipGraph or event), so it may itself be captured into a graph.  Meaning,
+ * inputs and outputs as qa_integrate (same points, sums and recompute rule;
+ * no fused-kernel timing), except: rounds hold at most 2^19 samples, and grid
+ * (0 = 16 waves per CU) is lowered to the largest multiple of 4 whose
+ * per-wave buffers fit the array next to a round's records.  With one round
+ * and the same tile and grid the sums are bit-identical to qa_integrate's.
+ * QA_ECAP if not even 4 waves fit (a set of thousands of graphs).  Every call
+ * on a GPU uses that GPU's one array, which keeps the last call's contents:
+ * calls that overlap on one GPU (two streams or threads) race and must be
+ * serialised by the caller. */
+int qa_integrate_noalloc(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t first, uint64_t seed,
+                         uint32_t tag, uint32_t tile, uint32_t grid, qa_acc* acc, void* stream);
+
 /* Autotuner of the batched form: for each candidate tile (256, 512, 1024
  * samples; a fused workgroup of 256 lanes takes tile/256 samples per lane)
  * and grid (16, 12 and 8 persistent waves per CU), runs qa_integrate twice on

@@ -75,6 +75,7 @@ def lib():
         L.qa_variance_gradient.argtypes = [vp, vp, u32, u64, u32, u64, u64, vp, vp, C.POINTER(C.c_double), vp]
         L.qa_acc_merge.argtypes = [vp, vp, sz]
         L.qa_graph_flops_nonzero.argtypes = [vp, u32, C.POINTER(C.c_double)]
+        L.qa_integrate_noalloc.argtypes = [vp, vp, vp, u64, u64, u32, u32, u32, vp, vp]
         _lib = L
     return _lib
 
@@ -357,6 +358,18 @@ def integrate(gset, img, budgets, seed, tag=0, tile=0, grid=0, work=None, acc=No
                               _ptr(work), work.numel(), _ptr(acc), C.byref(ms) if timing else None,
                               _stream(stream)), "qa_integrate")
     return (acc, ms.value) if timing else acc
+
+
+def integrate_noalloc(gset, img, budgets, seed, tag=0, tile=0, grid=0, acc=None, first=0, stream=None):
+    """qa_integrate_noalloc: the batched form on the library's scratch array
+    (no work buffer, no allocation in the call; acc must be passed to keep the
+    call itself allocation-free)."""
+    b = np.ascontiguousarray(budgets, dtype=np.uint64)
+    if acc is None:
+        acc = new_acc(len(gset), img.buf.device)
+    _check(lib().qa_integrate_noalloc(gset.h, img.ptr, b.ctypes.data_as(C.c_void_p), first, seed, tag, tile, grid,
+                                      _ptr(acc), _stream(stream)), "qa_integrate_noalloc")
+    return acc
 
 
 def allocate_budgets(gset, pilot, total, floor=0):

@@ -1187,6 +1187,151 @@ extern "C" int qa_integrate(const qa_set* s, const void* dev, const uint64_t* bu
     return QA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched form without allocation: the work memory is the library's own
+// device array `scratch` (one per GPU, reserved when the code object is
+// loaded on that GPU, held until the process ends); budgets travel in kernel
+// arguments and every buffer that must start at zero is cleared by a kernel,
+// so the call enqueues only kernel launches on the caller's stream.
+
+constexpr size_t kScratchBytes = 384ull << 20;
+constexpr uint64_t kNoAllocRoundSamples = 1ull << 19;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];
+
+// device address of this GPU's `scratch` (the array's name in host code is a
+// host-side stand-in, not a device address)
+static int scratch_address(void** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return qa_fail(QA_ENOTSUP, "device index beyond 63");
+    std::lock_guard<std::mutex> l(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return qa_fail(QA_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QA_OK;
+}
+
+constexpr int kBudgetChunk = 48;
+struct BudgetChunk {
+    uint32_t off, cnt;
+    uint64_t b[kBudgetChunk];
+};
+__global__ void k_put_budgets(Work w, BudgetChunk c) {
+    const uint32_t i = threadIdx.x;
+    if (i < c.cnt) w.budget[c.off + i] = c.b[i];
+}
+// counters to zero, the call's key and first sample, the graphs' first tiles
+// (prefix over the budgets) and acc cleared: one wave
+__global__ void k_setup(Work w, qa_acc* acc, uint32_t seed, uint32_t tag, uint64_t first) {
+    const uint32_t lane = threadIdx.x;
+    if (lane < 16) {
+        uint32_t v = 0;
+        if (lane == kCKey) v = seed;
+        if (lane == kCKey + 1) v = tag;
+        if (lane == kCFirst) v = (uint32_t)first;
+        if (lane == kCFirst + 1) v = (uint32_t)(first >> 32);
+        w.counter[lane] = v;
+    }
+    for (uint32_t g = lane; g < w.ng; g += 64) acc[g] = qa_acc{};
+    if (lane == 0) {
+        uint64_t t = 0;
+        for (uint32_t g = 0; g < w.ng; ++g) {
+            w.gtile0[g] = t;
+            t += (w.budget[g] + w.tile - 1) / w.tile;
+        }
+        w.gtile0[w.ng] = t;
+    }
+}
+
+
+// rounds of at most kNoAllocRoundSamples samples; the largest grid (a multiple
+// of the fused workgroup, at most the requested one) whose work fits scratch
+static int noalloc_plan(size_t ng, const uint64_t* budgets, uint32_t tile, uint32_t grid, uint64_t& ntiles,
+                        uint32_t& per_round, uint32_t& grid_out, WorkLayout& L) {
+    ntiles = 0;
+    for (size_t g = 0; g < ng; ++g) ntiles += (budgets[g] + tile - 1) / tile;
+    per_round = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ntiles, std::max<uint64_t>(1, kNoAllocRoundSamples / tile)));
+    const size_t fixed = work_layout(ng, tile, per_round, 0).total;
+    const size_t per_wave = (work_layout(ng, tile, per_round, 64 * kFusedWaves).total - fixed) / 64;
+    if (fixed + per_wave > kScratchBytes) return qa_fail(QA_ECAP, "set does not fit the no-allocation scratch");
+    if (grid == 0) grid = default_grid();
+    grid = std::min<uint32_t>(grid, (uint32_t)std::min<size_t>(kMaxWaves, (kScratchBytes - fixed) / per_wave * kFusedWaves));
+    grid = grid / kFusedWaves * kFusedWaves;
+    while (grid > 0 && work_layout(ng, tile, per_round, grid).total > kScratchBytes) grid -= kFusedWaves;
+    if (grid == 0) return qa_fail(QA_ECAP, "no persistent wave fits the no-allocation scratch");
+    grid_out = grid;
+    L = work_layout(ng, tile, per_round, grid);
+    return QA_OK;
+}
+
+extern "C" int qa_integrate_noalloc(const qa_set* s, const void* dev, const uint64_t* budgets, uint64_t first,
+                                    uint64_t seed, uint32_t tag, uint32_t tile, uint32_t grid, qa_acc* acc,
+                                    void* stream) {
+    auto img = image_of(dev);
+    if (!img) return qa_fail(QA_EINVAL, "device image not uploaded by qa_upload");
+    if (!s || !budgets || !acc) return qa_fail(QA_EINVAL, "NULL argument");
+    if (seed >> 32) return qa_fail(QA_EINVAL, "seed must be below 2^32 (32-bit Philox key word)");
+    const size_t ng = qa_set_size(s);
+    if (ng == 0) return qa_fail(QA_EINVAL, "empty set");
+    if (reinterpret_cast<const DevHeader*>(img->data())->ngraphs != ng) return qa_fail(QA_EINVAL, "set / image mismatch");
+    if (tile == 0) tile = kDefaultTile;
+    if (tile % 64) return qa_fail(QA_EINVAL, "tile must be a multiple of 64");
+    if (grid > kMaxWaves) return qa_fail(QA_EINVAL, "grid too large (max 4096 waves)");
+    for (size_t g = 0; g < ng; ++g)
+        if (host_graph(*img, (uint32_t)g)->npoly > QA_MAXPOLY) return qa_fail(QA_ENOTSUP, "too many piece-result slots");
+    uint64_t ntiles = 0;
+    uint32_t per_round = 0;
+    WorkLayout L{};
+    if (int rc = noalloc_plan(ng, budgets, tile, grid, ntiles, per_round, grid, L)) return rc;
+    void* base = nullptr;
+    if (int rc = scratch_address(&base)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Work w{};
+    set_work(w, (char*)base, L);
+    w.grid = grid;
+    w.tile = tile;
+    w.per_round = per_round;
+    w.ng = (uint32_t)ng;
+    w.ntiles = ntiles;
+    for (size_t off = 0; off < ng; off += kBudgetChunk) {
+        BudgetChunk c{};
+        c.off = (uint32_t)off;
+        c.cnt = (uint32_t)std::min<size_t>(kBudgetChunk, ng - off);
+        for (uint32_t i = 0; i < c.cnt; ++i) c.b[i] = budgets[off + i];
+        hipLaunchKernelGGL(k_put_budgets, dim3(1), dim3(64), 0, st, w, c);
+    }
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, w, acc, (uint32_t)seed, tag, first);
+    HIPCHK(hipGetLastError());
+    if (ntiles == 0) return QA_OK;
+    const size_t lds_fp = sizeof(double) * (QA_NVAR - QA_VAR_A) * kFusedThreads,
+                 lds_dd = sizeof(DD) * (QA_NVAR - QA_VAR_A) * 64;
+    if (int rc = lds_attr(k_fused, lds_fp)) return rc;
+    if (int rc = lds_attr(k_fix_dd, lds_dd)) return rc;
+    const uint64_t rounds = (ntiles + per_round - 1) / per_round;
+    const dim3 gng((unsigned)ng);
+    for (uint64_t r = 0; r < rounds; ++r) {
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, w);
+        hipLaunchKernelGGL(k_fused, dim3(grid / kFusedWaves), dim3(kFusedThreads), lds_fp, st, (const uint8_t*)dev, w);
+        hipLaunchKernelGGL(k_scale, gng, dim3(64), 0, st, w, acc);
+        hipLaunchKernelGGL(k_select, dim3(grid), dim3(64), 0, st, w);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, w);
+        hipLaunchKernelGGL(k_compact, dim3(grid), dim3(64), 0, st, w);
+        hipLaunchKernelGGL(k_fix_dd, dim3(grid), dim3(64), lds_dd, st, (const uint8_t*)dev, w);
+        hipLaunchKernelGGL(k_fix_combine, dim3(512), dim3(256), 0, st, w);
+        hipLaunchKernelGGL(k_reduce, gng, dim3(64), 0, st, w, acc);
+        hipLaunchKernelGGL(k_next_round, dim3(1), dim3(64), 0, st, w);
+        HIPCHK(hipGetLastError());
+    }
+    return QA_OK;
+}
+
 // Autotuner of the batched form: times the fused pass on a pilot share of the
 // budgets for each candidate (tile, grid) and returns the fastest per sample.
 // A fused workgroup of 256 lanes takes tile / 256 samples per lane (the
