@@ -34,15 +34,28 @@ def tune(gset, pdf, img, seed, samples, steps, step_size, floor=0.5, tag=1, devi
     return pdf, img, hist
 
 
-def production(gset, img, seed, total, pilot_per_graph, floor_frac=0.25, pilot_tag=1, tag=0, work=None):
+def production(gset, img, seed, total, pilot_per_graph, floor_frac=0.25, pilot_tag=1, tag=0, work=None, chunks=1,
+               log=None):
     """Frozen PDFs: a pilot of `pilot_per_graph` samples per graph (tag
     `pilot_tag`), Neyman budgets summing to `total` (each graph at least
-    floor_frac * total / graphs), then the production integral (tag `tag`).
-    Returns (per-graph results, set total, budgets)."""
-    from . import acc_read, allocate_budgets, integrate, read_acc
+    floor_frac * total / graphs), then the production integral (tag `tag`)
+    in `chunks` calls whose sums the library merges.  Chunk c draws sample
+    indices [c B, c B + its share) of every graph's stream, B the largest
+    share, so the chunks never reuse a sample.  Returns (per-graph results,
+    set total, budgets)."""
+    from . import acc_merge, allocate_budgets, integrate, read_acc, results, ACC_DTYPE
     ng = len(gset)
     pilot = read_acc(integrate(gset, img, np.full(ng, pilot_per_graph, dtype=np.uint64), seed, pilot_tag, work=work))
     budgets = allocate_budgets(gset, pilot, int(total), int(floor_frac * total / ng))
-    acc = integrate(gset, img, budgets, seed, tag, work=work)
-    per, tot = acc_read(gset, acc)
+    merged = np.zeros(ng, dtype=ACC_DTYPE)
+    done = np.zeros(ng, dtype=np.uint64)
+    B = int(-(-int(budgets.max()) // chunks))
+    for c in range(chunks):
+        part = np.minimum(budgets - done, np.uint64(B))
+        merged = acc_merge(merged, read_acc(integrate(gset, img, part, seed, tag, work=work, first=c * B)))
+        done += part
+        if log:
+            _, tot = results(gset, merged)
+            log(f"production chunk {c + 1}/{chunks}: {tot['value']:.6g} +- {tot['sigma']:.3g} over {int(tot['n'])} samples")
+    per, tot = results(gset, merged)
     return per, tot, budgets
