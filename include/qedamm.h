@@ -152,7 +152,27 @@ int qa_combine(const qa_result* runs, size_t nruns, qa_result* out);
  * W(full) = sum_j W(full\j). */
 int qa_pdf_create(const qa_set* s, const double* deg, qa_pdf** out);
 void qa_pdf_destroy(qa_pdf* p);
-/* Copy graph i's Deg and W tables (2^(3n) doubles each; either may be NULL). */
+/* The paper's 3n-2 variables (section "The method", footnote): at q = 0 the
+ * two electron lines next to the external vertex, a = x-1 and b = x, carry
+ * the same momentum and the integrand is linear in their split, so the
+ * integral over the split is exact at the even split: with s = z_a + z_b,
+ *   int f dz = int over the 3n-1 merged parameters of s f(.., s/2, s/2, ..).
+ * qa_pdf_create_merged makes, from an unmerged base pdf, the PDF of eq. (1)
+ * over the 3n-1 merged lines (merged line j is line j for j < b and line
+ * j+1 for j >= b; line a stands for {a, b}) with Deg'(S') = Deg(S) for the
+ * original set S of S'.  An image uploaded with a merged pdf samples the
+ * merged lines: qa_sample_pdf then returns z of all 3n lines (a and b at
+ * s/2 each), log p of the merged density minus ln s (so that f exp(-log p)
+ * is the merged weight) and sector rows 0..3n-2 (row 3n-1 = 255);
+ * qa_integrate, qa_variance_grad and qa_variance_gradient use the merged
+ * form throughout (gradient over the 2^(3n-1) merged sets).  QA_EINVAL if
+ * base is already merged. */
+int qa_pdf_create_merged(const qa_set* s, const qa_pdf* base, qa_pdf** out);
+/* Lines the pdf samples for graph i: 3n, or 3n-1 for a merged pdf (its
+ * tables hold 2^lines doubles). */
+int qa_pdf_lines(const qa_pdf* p, uint32_t graph, int* lines);
+
+/* Copy graph i's Deg and W tables (2^lines doubles each, qa_pdf_lines; either may be NULL). */
 int qa_pdf_tables(const qa_pdf* p, uint32_t graph, double* deg, double* w);
 /* Gradient of ln W(full) with respect to Deg(S) for graph i (2^(3n) doubles). */
 int qa_pdf_dlogw(const qa_pdf* p, uint32_t graph, double* out);

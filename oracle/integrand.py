@@ -536,3 +536,31 @@ class Integrand:
         if return_terms:
             return float(tot), [float(v) for v in vals]
         return float(tot)
+
+
+# Gauss-Legendre nodes and weights on [0, 1], three points (exact for
+# polynomials of degree <= 5 in the split)
+_GL3 = ((0.5 - 0.5 * (3.0 / 5.0) ** 0.5, 5.0 / 18.0), (0.5, 8.0 / 18.0), (0.5 + 0.5 * (3.0 / 5.0) ** 0.5, 5.0 / 18.0))
+
+
+class MergedIntegrand:
+    """The 3n-2-variable integrand (paper's footnote on 3n-1 -> 3n-2): with
+    s = z_a + z_b the parameter of the two electron lines next to the external
+    vertex (a = x-1, b = x), f_m(s, rest) = s * int_0^1 f(t s, (1-t) s, rest) dt,
+    the split integrated by three-point Gauss-Legendre (the integrand is a
+    polynomial of low degree in t; see tests)."""
+
+    def __init__(self, g):
+        from .pdf import expand_point
+        self.g = g
+        self.f = Integrand(g)
+        self._expand = expand_point
+
+    def __call__(self, zm, nodes=_GL3):
+        from .pdf import merged_lines
+        a, _ = merged_lines(self.g)
+        s = float(zm[a])
+        tot = 0.0
+        for t, w in nodes:
+            tot += w * self.f(self._expand(self.g, np.asarray(zm, dtype=float), t))
+        return s * tot

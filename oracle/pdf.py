@@ -178,3 +178,54 @@ def sample_stream(g, deg, W, seed, tag, graph, first, count):
         u = uniforms(seed, tag, graph, i, 2 * (M - 1))
         out.append(sample(deg, W, M, u))
     return out
+
+
+# ----------------------------------------------------------------------------
+# 3n-2 variables (the paper's footnote on reducing 3n-1 to 3n-2): at q = 0 the
+# two electron lines next to the external vertex, a = x-1 and b = x, carry
+# the same momentum, so the integral over their split is done before the
+# Monte Carlo: the pair becomes one "merged" line with parameter s = z_a + z_b
+# and the remaining 3n-1 parameters live on a simplex of dimension 3n-2.
+# Merged line j stands for original line j (j < b) or j + 1 (j >= b); merged
+# line a stands for {a, b}.
+
+def merged_lines(g):
+    """(a, b) of the merged pair."""
+    x = g["x"]
+    return x - 1, x
+
+
+def expand_set(g, Sm):
+    """Original line set of a merged-line set."""
+    a, b = merged_lines(g)
+    low = Sm & ((1 << b) - 1)
+    high = (Sm >> b) << (b + 1)
+    out = low | high
+    if Sm >> a & 1:
+        out |= 1 << b
+    return out
+
+
+def merged_deg_table(g, D):
+    """Deg over the merged lines: Deg'(S') = Deg(expand(S'))."""
+    Mm = 3 * g["n"] - 1
+    full = (1 << Mm) - 1
+    Dm = np.zeros(1 << Mm)
+    for S in range(1, full):
+        Dm[S] = D[expand_set(g, S)]
+    return Dm
+
+
+def expand_point(g, zm, t=0.5):
+    """Original parameters from merged ones, split t : 1-t on (a, b)."""
+    a, b = merged_lines(g)
+    s = zm[a]
+    z = np.concatenate([zm[:b], [0.0], zm[b:]])
+    z[a], z[b] = t * s, (1.0 - t) * s
+    return z
+
+
+def sample_merged(g, Dm, Wm, u):
+    """One point of the merged form: (merged z, log p of the merged density,
+    sector) from eq. (1) over the 3n-1 merged lines."""
+    return sample(Dm, Wm, 3 * g["n"] - 1, u)

@@ -74,6 +74,8 @@ def lib():
         L.qa_pdf_tune.argtypes = [vp, u32, vp, C.c_double, C.c_double, C.POINTER(vp), vp]
         L.qa_variance_gradient.argtypes = [vp, vp, u32, u64, u32, u64, u64, vp, vp, C.POINTER(C.c_double), vp]
         L.qa_acc_merge.argtypes = [vp, vp, sz]
+        L.qa_pdf_create_merged.argtypes = [vp, vp, C.POINTER(vp)]
+        L.qa_pdf_lines.argtypes = [vp, u32, C.POINTER(C.c_int)]
         L.qa_graph_flops_nonzero.argtypes = [vp, u32, C.POINTER(C.c_double)]
         L.qa_integrate_noalloc.argtypes = [vp, vp, vp, u64, u64, u32, u32, u32, vp, vp]
         _lib = L
@@ -177,8 +179,20 @@ class Pdf:
         _check(lib().qa_pdf_create(gset.h, dptr, C.byref(h)), "qa_pdf_create")
         self.h = h
 
+    def lines(self, g):
+        """Lines sampled for graph g: 3n, or 3n - 1 for a merged pdf."""
+        m = C.c_int()
+        _check(lib().qa_pdf_lines(self.h, g, C.byref(m)), "qa_pdf_lines")
+        return m.value
+
+    def merged(self):
+        """qa_pdf_create_merged: the 3n-2-variable form of this (unmerged) pdf."""
+        h = C.c_void_p()
+        _check(lib().qa_pdf_create_merged(self.gset.h, self.h, C.byref(h)), "qa_pdf_create_merged")
+        return Pdf(self.gset, _handle=h)
+
     def tables(self, g):
-        M = 3 * self.gset.graphs[g].loops
+        M = self.lines(g)
         D = np.zeros(1 << M)
         W = np.zeros(1 << M)
         _check(lib().qa_pdf_tables(self.h, g, D.ctypes.data_as(C.c_void_p), W.ctypes.data_as(C.c_void_p)),
@@ -186,7 +200,7 @@ class Pdf:
         return D, W
 
     def dlogw(self, g):
-        M = 3 * self.gset.graphs[g].loops
+        M = self.lines(g)
         out = np.zeros(1 << M)
         _check(lib().qa_pdf_dlogw(self.h, g, out.ctypes.data_as(C.c_void_p)), "qa_pdf_dlogw")
         return out
@@ -194,7 +208,7 @@ class Pdf:
     def with_graph(self, g, deg):
         """A new Pdf equal to this one except graph g's Deg table."""
         d = np.ascontiguousarray(deg, dtype=np.float64)
-        if d.shape != (1 << (3 * self.gset.graphs[g].loops),):
+        if d.shape != (1 << self.lines(g),):
             raise RuntimeError("deg must hold 2^M entries")
         h = C.c_void_p()
         _check(lib().qa_pdf_with(self.h, g, d.ctypes.data_as(C.c_void_p), C.byref(h)), "qa_pdf_with")
@@ -202,7 +216,7 @@ class Pdf:
 
     def tune(self, g, grad, step, floor=0.5):
         """One pilot step on graph g (qa_pdf_tune): returns (new Pdf, shifts per set size)."""
-        M = 3 * self.gset.graphs[g].loops
+        M = self.lines(g)
         gr = np.ascontiguousarray(grad, dtype=np.float64)
         if gr.shape != (1 << M,):
             raise RuntimeError("grad must hold 2^M entries")
@@ -402,7 +416,7 @@ def autotune(gset, img, budgets, seed, tag=0, pilot=0, work=None, stream=None):
 
 def variance_grad(img, graph, seed, tag, first, count, grad=None, w2sum=None, stream=None):
     import torch
-    M = _lines(img, graph)
+    M = img.pdf.lines(graph)
     dev = img.buf.device
     if grad is None:
         grad = torch.zeros(1 << M, dtype=torch.float64, device=dev)
@@ -417,7 +431,8 @@ def variance_gradient(pdf, img, graph, seed, tag, first, count, stream=None):
     """qa_variance_gradient: (E[w^2], d E[w^2] / d Deg(S) for all S) of one graph
     on samples first..first+count-1; pdf must be the one img was uploaded from."""
     import torch
-    M = _lines(img, graph)
+    _lines(img, graph)
+    M = pdf.lines(graph)
     work = torch.empty((1 << M) + 1, dtype=torch.float64, device=img.buf.device)
     grad = np.zeros(1 << M)
     m2 = C.c_double()

@@ -24,7 +24,8 @@ struct qa_set {
     std::vector<GraphTables> graphs;
 };
 struct qa_pdf {
-    std::vector<int> M;
+    std::vector<int> M;                        // sampled lines per graph (3n, or 3n - 1 in the merged form)
+    std::vector<int> mb;                       // merged form: line b of the merged pair, else -1
     std::vector<std::vector<double>> deg, w;
 };
 
@@ -409,6 +410,7 @@ extern "C" int qa_pdf_create(const qa_set* s, const double* deg, qa_pdf** out) {
             } else D = default_deg(T.g);
             off += size_t(1) << M;
             p->M.push_back(M);
+            p->mb.push_back(-1);
             p->w.push_back(w_table(D, M));
             p->deg.push_back(std::move(D));
         }
@@ -418,6 +420,41 @@ extern "C" int qa_pdf_create(const qa_set* s, const double* deg, qa_pdf** out) {
 }
 
 void qa_image_forget(const void* s, const void* p);
+// 3n-2 variables: Deg'(S') = Deg(expand(S')) over the merged lines (line j
+// stands for j (j < b) or j + 1 (j >= b); line a = b - 1 stands for {a, b})
+static uint32_t expand_merged(uint32_t Sm, int b) {
+    const uint32_t low = Sm & ((1u << b) - 1), high = (Sm >> b) << (b + 1);
+    return low | high | (((Sm >> (b - 1)) & 1u) << b);
+}
+
+extern "C" int qa_pdf_create_merged(const qa_set* s, const qa_pdf* base, qa_pdf** out) {
+    try {
+        if (!s || !base || !out) return fail(QA_EINVAL, "NULL argument");
+        if (base->M.size() != s->graphs.size()) return fail(QA_EINVAL, "set / pdf mismatch");
+        auto* p = new qa_pdf;
+        for (size_t gi = 0; gi < s->graphs.size(); ++gi) {
+            const Graph& g = s->graphs[gi].g;
+            const int M = 3 * g.n, Mm = M - 1, b = g.x;
+            if (base->mb[gi] >= 0 || base->M[gi] != M) { delete p; return fail(QA_EINVAL, "base pdf is already merged"); }
+            if (b < 1 || b > 2 * g.n - 1) { delete p; return fail(QA_EINVAL, "external vertex without two internal electron lines"); }
+            std::vector<double> D(size_t(1) << Mm, 0.0);
+            for (uint32_t S = 1; S + 1 < (1u << Mm); ++S) D[S] = base->deg[gi][expand_merged(S, b)];
+            p->M.push_back(Mm);
+            p->mb.push_back(b);
+            p->w.push_back(w_table(D, Mm));
+            p->deg.push_back(std::move(D));
+        }
+        *out = p;
+        return QA_OK;
+    } catch (std::exception& e) { return fail(QA_ENOMEM, e.what()); }
+}
+
+extern "C" int qa_pdf_lines(const qa_pdf* p, uint32_t graph, int* lines) {
+    if (!p || graph >= p->M.size() || !lines) return fail(QA_EINVAL, "bad argument");
+    *lines = p->M[graph];
+    return QA_OK;
+}
+
 extern "C" void qa_pdf_destroy(qa_pdf* p) {
     qa_image_forget(nullptr, p);
     delete p;
@@ -513,11 +550,12 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
     }
     for (size_t gi = 0; gi < s->graphs.size(); ++gi) {
         const auto& T = s->graphs[gi];
-        const int M = 3 * T.g.n;
-        uint64_t doff = P.alloc(8u << M, 256);
-        std::memcpy(P.buf.data() + doff, p->deg[gi].data(), 8u << M);
-        uint64_t woff = P.alloc(8u << M, 256);
-        std::memcpy(P.buf.data() + woff, p->w[gi].data(), 8u << M);
+        const int M = 3 * T.g.n, Ms = p->M[gi];
+        if (Ms != (p->mb[gi] >= 0 ? M - 1 : M)) return fail(QA_EINVAL, "pdf does not match the set's graphs");
+        uint64_t doff = P.alloc(8u << Ms, 256);
+        std::memcpy(P.buf.data() + doff, p->deg[gi].data(), 8u << Ms);
+        uint64_t woff = P.alloc(8u << Ms, 256);
+        std::memcpy(P.buf.data() + woff, p->w[gi].data(), 8u << Ms);
         uint64_t toff = P.alloc(sizeof(DevTerm) * T.terms.size(), 64);
         int npoly_max = 0;
         for (size_t ti = 0; ti < T.terms.size(); ++ti) {
@@ -638,6 +676,7 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
         DevGraph dg{};
         dg.n = T.g.n; dg.M = M; dg.mult = T.g.mult; dg.nterms = (int)T.terms.size();
         dg.deg_off = doff; dg.w_off = woff; dg.terms_off = toff; dg.npoly = std::max(1, npoly_max);
+        dg.mb = p->mb[gi];
         std::memcpy(P.buf.data() + goff + gi * sizeof(DevGraph), &dg, sizeof dg);
     }
     out.swap(P.buf);

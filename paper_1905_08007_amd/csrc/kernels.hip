@@ -56,7 +56,7 @@ struct Stream {
 // sector-tree sampling from eq. (1): choose j_1..j_M with P(j | S) =
 // W(S\j) / sum_j' W(S\j'), then t_l ~ Exp(Deg(S_l)) and ln z_{j_l} = -sum t.
 // Writes z (normalised) through zv, returns log p; order[l] = j_(l+1).
-__device__ __forceinline__ bool sample_point(const QA_RO double* D, const QA_RO double* W, int M, const Stream& st,
+__device__ __forceinline__ bool sample_lines(const QA_RO double* D, const QA_RO double* W, int M, const Stream& st,
                              LV<double> zv, double& logp, uint8_t* order, double* tl) {
     const uint32_t full = (1u << M) - 1;
     uint32_t S = full;
@@ -118,6 +118,27 @@ __device__ __forceinline__ bool sample_point(const QA_RO double* D, const QA_RO 
     return ok && isfinite(logp);
 }
 
+// A point of graph G: all M lines from eq. (1), or in the merged form (the
+// paper's 3n-2 variables, mb >= 0) the M - 1 merged lines, whose merged
+// parameter s is split evenly over its two lines a = mb - 1, b = mb (the
+// integrand is linear in the split, so s f(s/2, s/2, ...) is the exact split
+// integral); logp then carries -ln s, so that f exp(-logp) is the merged
+// weight.  order and tl are over the sampled lines.
+__device__ __forceinline__ bool sample_point(const QA_RO double* D, const QA_RO double* W, int M, int mb,
+                                             const Stream& st, LV<double> zv, double& logp, uint8_t* order,
+                                             double* tl) {
+    if (mb < 0) return sample_lines(D, W, M, st, zv, logp, order, tl);
+    bool ok = sample_lines(D, W, M - 1, st, zv, logp, order, tl);
+    const double sm = zv[mb - 1];
+#pragma unroll
+    for (int i = QA_MAXM - 1; i > 0; --i)
+        if (i > mb && i < M) zv[i] = zv[i - 1];
+    zv[mb - 1] = 0.5 * sm;
+    zv[mb] = 0.5 * sm;
+    logp -= log(sm);
+    return ok && isfinite(logp);
+}
+
 __device__ __forceinline__ const QA_RO DevGraph& dev_graph(const QA_RO uint8_t* img, uint32_t g) {
     const QA_RO DevHeader* h = reinterpret_cast<const QA_RO DevHeader*>(img);
     return reinterpret_cast<const QA_RO DevGraph*>(img + h->graphs_off)[g];
@@ -136,10 +157,11 @@ __global__ void __launch_bounds__(256) k_sample(const uint8_t* __restrict__ img_
     uint8_t order[QA_MAXM];
     double tl[QA_MAXM];
     double lp;
-    sample_point(D, W, G.M, st, LV<double>{z + i, (int)count}, lp, order, tl);
+    sample_point(D, W, G.M, G.mb, st, LV<double>{z + i, (int)count}, lp, order, tl);
     logp[i] = lp;
+    const int Ms = G.mb >= 0 ? G.M - 1 : G.M;
     if (sector)
-        for (int l = 0; l < G.M; ++l) sector[(uint64_t)l * count + i] = order[l];
+        for (int l = 0; l < G.M; ++l) sector[(uint64_t)l * count + i] = l < Ms ? order[l] : 0xff;
 }
 
 // ---------------------------------------------------------------------------
@@ -492,7 +514,7 @@ __global__ void __launch_bounds__(kFusedThreads, kFusedOcc) k_fused(const uint8_
                 double tl[QA_MAXM];
                 double lp;
                 LV<double> zv{zb + lane, 64};
-                bool ok = sample_point(D, W, G.M, st, zv, lp, order, tl);
+                bool ok = sample_point(D, W, G.M, G.mb, st, zv, lp, order, tl);
                 if (ok) {
                     double cond;
                     ER r = eval_point<ER>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond);
@@ -731,7 +753,7 @@ __global__ void __launch_bounds__(64) k_fix_dd(const uint8_t* __restrict__ img_,
                 uint8_t order[QA_MAXM];
                 double tl[QA_MAXM], lp, cond;
                 LV<double> zv{zb + lane, 64};
-                sample_point(D, W, G.M, st, zv, lp, order, tl);
+                sample_point(D, W, G.M, G.mb, st, zv, lp, order, tl);
                 const DD r = eval_point<DD>(img, G, CLV<double>{zb + lane, 64}, vars, polys, cond, (int)j, (int)ns);
                 w.fpart[(uint64_t)idx * ns + j] = r;
                 if (j == 0) w.fcond[idx] = cond;
@@ -822,13 +844,14 @@ __global__ void __launch_bounds__(64) k_vargrad(const uint8_t* __restrict__ img_
         uint8_t order[QA_MAXM];
         double tl[QA_MAXM], lp, cond;
         LV<double> zv{zb + threadIdx.x, (int)blockDim.x};
-        if (sample_point(D, W, G.M, st, zv, lp, order, tl)) {
+        if (sample_point(D, W, G.M, G.mb, st, zv, lp, order, tl)) {
             const double f = eval_point<double>(img, G, CLV<double>{zb + threadIdx.x, (int)blockDim.x}, vars, polys, cond);
             const double w = f * exp(-lp);
             if (isfinite(w)) {
                 w2 = w * w;
-                uint32_t S = (1u << G.M) - 1;
-                for (int l = 1; l < G.M; ++l) {
+                const int Ms = G.mb >= 0 ? G.M - 1 : G.M;
+                uint32_t S = (1u << Ms) - 1;
+                for (int l = 1; l < Ms; ++l) {
                     S ^= 1u << order[l - 1];
                     atomicAdd(grad + S, w2 * tl[l]);
                 }
@@ -1425,12 +1448,13 @@ extern "C" int qa_variance_gradient(const qa_pdf* p, const void* dev, uint32_t g
     const DevGraph* G = host_graph(*img, graph);
     if (!G) return qa_fail(QA_EINVAL, "graph index out of range");
     const std::vector<double>* D = qa_pdf_deg(p, graph);
-    if (!D || D->size() != (size_t(1) << G->M)) return qa_fail(QA_EINVAL, "pdf does not match the image");
+    const int Ms = G->mb >= 0 ? G->M - 1 : G->M;
+    if (!D || D->size() != (size_t(1) << Ms)) return qa_fail(QA_EINVAL, "pdf does not match the image");
     if (std::memcmp(D->data(), img->data() + G->deg_off, 8 * D->size()) != 0)
         return qa_fail(QA_EINVAL, "the image on dev was not uploaded from this pdf");
     if (!work || !grad) return qa_fail(QA_EINVAL, "NULL argument");
     if (count < 1) return qa_fail(QA_EINVAL, "count must be positive");
-    const size_t nS = size_t(1) << G->M;
+    const size_t nS = size_t(1) << Ms;
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipMemsetAsync(work, 0, 8 * (nS + 1), st));
     if (int rc = qa_variance_grad(dev, graph, seed, tag, first, count, work, work + nS, stream)) return rc;

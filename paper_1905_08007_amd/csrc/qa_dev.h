@@ -31,10 +31,10 @@ struct DevHeader {
 
 struct DevGraph {
     int32_t n, M, mult, nterms;
-    uint64_t deg_off, w_off;    // double[2^M]
+    uint64_t deg_off, w_off;    // double[2^Ms], Ms = M (mb < 0) or M - 1 (merged form)
     uint64_t terms_off;         // DevTerm[nterms]
     int32_t npoly;              // LDS polynomial slots used by any term
-    int32_t pad;
+    int32_t mb;                 // merged form: line b = x of the merged pair (a = b - 1, b); -1: all M lines sampled
 };
 
 struct DevTerm {

@@ -121,3 +121,22 @@ def test_acc_merge_and_nonzero_flops():
         dense, _ = s.flops(g)
         nz = s.flops_nonzero(g)
         assert 0 < nz <= dense
+
+
+def test_merged_pdf_tables_match_oracle():
+    """The 3n-2-variable form's tables (qa_pdf_create_merged) against the
+    oracle's merged Deg (Deg of the expanded set) and its W recursion."""
+    from oracle import graphs as GR
+    for n in (1, 2, 3):
+        gs = P.enumerate_graphs(n)[:6]
+        s = P.build_forests(gs, 2)
+        p = P.pdf_create(s)
+        q = p.merged()
+        for i, g in enumerate(GR.enumerate_graphs(n)[:6]):
+            assert q.lines(i) == 3 * n - 1 and p.lines(i) == 3 * n
+            Dm, Wm = q.tables(i)
+            Do = PD.merged_deg_table(g, PD.deg_table(g))
+            assert np.array_equal(Dm, Do)
+            assert np.array_equal(Wm, PD.w_table(Do, 3 * n - 1))
+        with pytest.raises(RuntimeError):
+            q.merged()
