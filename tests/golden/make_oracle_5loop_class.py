@@ -3,10 +3,11 @@ of the 5-loop class (5,0,0), the oracle's first Philox points of the
 benchmark stream (seed 5, tag 0, samples 0..4): z, log p, sector, f and
 w = f / p.
 
-Calls only ``oracle/``.  f is evaluated in long double; a point whose forest
-terms cancel by more than 10^6 (sum |terms| > 10^6 |f|) is re-evaluated at
-60 significant digits, so every stored f carries a relative error far below
-the 1e-10 parity bar.
+Calls only ``oracle/``.  f is evaluated at 60 significant digits at every
+point: long double is not enough where the graph polynomials themselves are
+ill-conditioned (near a sector boundary one point lost ten digits in long
+double with its forest terms cancelling only by 10^5), and the stored f must
+carry a relative error far below the 1e-10 parity bar.
 Usage: python tests/golden/make_oracle_5loop_class.py
 """
 import json
@@ -33,17 +34,13 @@ def work(gi):
     out = []
     for i in SAMPLES:
         z, lp, order = PD.sample(D, W, 15, uniforms(SEED, TAG, gi, i, 28))
-        v, terms = f(z, True)
+        IN.set_precision("mp", 60)
+        try:
+            v, terms = f(z, True)
+        finally:
+            IN.set_precision("ld")
         tabs = sum(abs(t) for t in terms)
-        prec = "ld"
-        if tabs > 1e6 * abs(v):
-            IN.set_precision("mp")
-            try:
-                v, terms = f(z, True)
-            finally:
-                IN.set_precision("ld")
-            tabs = sum(abs(t) for t in terms)
-            prec = "mp60"
+        prec = "mp60"
         out.append({"sample": i, "z": [float(x) for x in z], "logp": lp, "order": list(order), "f": v,
                     "terms_abs": tabs, "w": v * math.exp(-lp), "prec": prec})
     return gi, {"x": g["x"], "mate": g["mate"], "mult": g["mult"], "nterms": len(f.terms), "philox": out,
