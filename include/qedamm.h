@@ -144,6 +144,15 @@ int qa_acc_merge(qa_acc* into, const qa_acc* from, size_t n);
  * eq. (2).  QA_EINVAL if any sigma is not positive and finite. */
 int qa_combine(const qa_result* runs, size_t nruns, qa_result* out);
 
+/* Sum of results of independent integrals (the nine gauge-invariant classes
+ * of Table 1 into the total of all graphs without lepton loops, or any
+ * disjoint graph sets): value = sum v_i, sigma = (sum s_i^2)^1/2, counts
+ * summed, mean = value, sd = sigma * sqrt(n) (as for a set total).  Section
+ * "Preliminary numerical results", Table 1: the class contributions add up to
+ * the whole set.  QA_EINVAL if any value or sigma is not finite or a sigma is
+ * negative. */
+int qa_sum_results(const qa_result* parts, size_t nparts, qa_result* out);
+
 /* Deg and W tables of eq. (1) for every graph of the set.  deg == NULL: the
  * default Deg rule (parametric UV degree of the I-closure, minimised over the
  * reduced graphs of all forests, floored at 1/2).  Otherwise deg holds, for
@@ -306,7 +315,8 @@ int qa_variance_gradient(const qa_pdf* p, const void* dev, uint32_t graph, uint6
                          uint64_t count, double* work, double* grad, double* m2, void* stream);
 
 /* Debug / test hook: exact Dirac trace of a symbol string (0 = on-shell
- * p-slash with p.p = 1; L > 0 = gamma contracted with the other L). */
+ * p-slash with p.p = 1; 0 < L < 32 = gamma contracted with the other L;
+ * at most 60 symbols; QA_EINVAL otherwise). */
 int qa_dirac_trace(const int32_t* sym, int len, double* out);
 
 #ifdef __cplusplus

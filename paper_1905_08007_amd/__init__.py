@@ -70,6 +70,7 @@ def lib():
         L.qa_results.argtypes = [vp, vp, vp, vp]
         L.qa_acc_read.argtypes = [vp, vp, vp, vp, vp]
         L.qa_combine.argtypes = [vp, sz, vp]
+        L.qa_sum_results.argtypes = [vp, sz, vp]
         L.qa_pdf_with.argtypes = [vp, u32, vp, C.POINTER(vp)]
         L.qa_pdf_tune.argtypes = [vp, u32, vp, C.c_double, C.c_double, C.POINTER(vp), vp]
         L.qa_variance_gradient.argtypes = [vp, vp, u32, u64, u32, u64, u64, vp, vp, C.POINTER(C.c_double), vp]
@@ -340,6 +341,14 @@ def combine(runs):
     r = np.ascontiguousarray(np.asarray(runs, dtype=RESULT_DTYPE).reshape(-1))
     out = np.zeros(1, dtype=RESULT_DTYPE)
     _check(lib().qa_combine(r.ctypes.data_as(C.c_void_p), len(r), out.ctypes.data_as(C.c_void_p)), "qa_combine")
+    return out[0]
+
+
+def sum_results(parts):
+    """qa_sum_results: the sum of results of independent integrals."""
+    r = np.ascontiguousarray(np.asarray(parts, dtype=RESULT_DTYPE).reshape(-1))
+    out = np.zeros(1, dtype=RESULT_DTYPE)
+    _check(lib().qa_sum_results(r.ctypes.data_as(C.c_void_p), len(r), out.ctypes.data_as(C.c_void_p)), "qa_sum_results")
     return out[0]
 
 

@@ -394,26 +394,65 @@ extern "C" int qa_combine(const qa_result* runs, size_t nruns, qa_result* out) {
     return QA_OK;
 }
 
+extern "C" int qa_sum_results(const qa_result* parts, size_t nparts, qa_result* out) {
+    if (!parts || !out || nparts == 0) return fail(QA_EINVAL, "NULL or empty argument");
+    double var = 0.0;
+    qa_result r{};
+    for (size_t i = 0; i < nparts; ++i) {
+        const double s = parts[i].sigma;
+        if (!(s >= 0.0) || !std::isfinite(s) || !std::isfinite(parts[i].value))
+            return fail(QA_EINVAL, "part " + std::to_string(i) + ": value and sigma must be finite, sigma >= 0");
+        r.value += parts[i].value;
+        var += s * s;
+        r.n += parts[i].n; r.n_bad += parts[i].n_bad; r.n_flagged += parts[i].n_flagged; r.n_residual += parts[i].n_residual;
+    }
+    r.sigma = std::sqrt(var);
+    r.mean = r.value;
+    r.sd = r.sigma * std::sqrt((double)r.n);
+    *out = r;
+    return QA_OK;
+}
+
 extern "C" int qa_pdf_create(const qa_set* s, const double* deg, qa_pdf** out) {
     try {
         if (!s || !out) return fail(QA_EINVAL, "NULL argument");
+        const size_t ng = s->graphs.size();
+        std::vector<size_t> off(ng + 1, 0);
+        for (size_t g = 0; g < ng; ++g) off[g + 1] = off[g] + (size_t(1) << (3 * s->graphs[g].g.n));
+        if (deg)
+            for (size_t g = 0; g < ng; ++g)
+                for (size_t x = off[g] + 1; x + 1 < off[g + 1]; ++x)
+                    if (!(deg[x] > 0.0) || !std::isfinite(deg[x])) return fail(QA_EINVAL, "Deg entries must be positive");
         auto* p = new qa_pdf;
-        size_t off = 0;
-        for (auto& T : s->graphs) {
-            int M = 3 * T.g.n;
-            std::vector<double> D;
-            if (deg) {
-                D.assign(deg + off, deg + off + (size_t(1) << M));
-                for (uint32_t x = 1; x + 1 < (1u << M); ++x)
-                    if (!(D[x] > 0.0) || !std::isfinite(D[x])) { delete p; return fail(QA_EINVAL, "Deg entries must be positive"); }
-                D[0] = 0.0; D[(1u << M) - 1] = 0.0;
-            } else D = default_deg(T.g);
-            off += size_t(1) << M;
-            p->M.push_back(M);
-            p->mb.push_back(-1);
-            p->w.push_back(w_table(D, M));
-            p->deg.push_back(std::move(D));
-        }
+        p->M.resize(ng);
+        p->mb.assign(ng, -1);
+        p->deg.resize(ng);
+        p->w.resize(ng);
+        // graphs are independent: one per host thread at a time
+        std::atomic<size_t> next{0};
+        std::string err;
+        std::mutex mu;
+        auto work = [&] {
+            for (size_t g; (g = next++) < ng;) {
+                try {
+                    const int M = 3 * s->graphs[g].g.n;
+                    std::vector<double> D;
+                    if (deg) {
+                        D.assign(deg + off[g], deg + off[g + 1]);
+                        D[0] = 0.0; D[(size_t(1) << M) - 1] = 0.0;
+                    } else D = default_deg(s->graphs[g].g);
+                    p->M[g] = M;
+                    p->w[g] = w_table(D, M);
+                    p->deg[g] = std::move(D);
+                } catch (std::exception& e) { std::lock_guard<std::mutex> l(mu); err = e.what(); }
+            }
+        };
+        const int nt = std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), (int)ng));
+        std::vector<std::thread> th;
+        for (int t = 1; t < nt; ++t) th.emplace_back(work);
+        work();
+        for (auto& t : th) t.join();
+        if (!err.empty()) { delete p; return fail(QA_ENOMEM, err); }
         *out = p;
         return QA_OK;
     } catch (std::exception& e) { return fail(QA_ENOMEM, e.what()); }

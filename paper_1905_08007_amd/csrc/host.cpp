@@ -247,22 +247,29 @@ std::vector<Piece> term_pieces(const Graph& g, const std::vector<Sub>& subs, uin
 // ---------------------------------------------------------------------------
 // Deg and W
 
-static int cyclomatic(const std::vector<std::array<int, 2>>& edges) {
-    if (edges.empty()) return 0;
-    std::vector<int> verts;
-    for (auto& e : edges) { verts.push_back(e[0]); verts.push_back(e[1]); }
-    std::sort(verts.begin(), verts.end());
-    verts.erase(std::unique(verts.begin(), verts.end()), verts.end());
-    std::vector<int> par(verts.size());
-    std::iota(par.begin(), par.end(), 0);
-    std::function<int(int)> f = [&](int a) { while (par[a] != a) a = par[a] = par[par[a]]; return a; };
-    auto id = [&](int v) { return (int)(std::lower_bound(verts.begin(), verts.end(), v) - verts.begin()); };
-    int comps = (int)verts.size();
-    for (auto& e : edges) {
-        int a = f(id(e[0])), b = f(id(e[1]));
-        if (a != b) { par[a] = b; --comps; }
+// cyclomatic number (edges - vertices + components) of the edges of a piece
+// whose line ids are in the set c; the piece's nodes are numbered 0..nodes-1
+struct PieceEdges {
+    int ne = 0;
+    int id[2 * QA_MAXL], a[2 * QA_MAXL], b[2 * QA_MAXL];
+};
+
+static int cyclomatic(const PieceEdges& E, uint32_t c) {
+    int par[2 * QA_MAXL + 2];
+    uint32_t touched = 0;
+    int edges = 0, merges = 0;
+    for (int e = 0; e < E.ne; ++e) {
+        if (!(c >> E.id[e] & 1)) continue;
+        ++edges;
+        int x = E.a[e], y = E.b[e];
+        if (!(touched >> x & 1)) { touched |= 1u << x; par[x] = x; }
+        if (!(touched >> y & 1)) { touched |= 1u << y; par[y] = y; }
+        while (par[x] != x) x = par[x] = par[par[x]];
+        while (par[y] != y) y = par[y] = par[par[y]];
+        if (x != y) { par[x] = y; ++merges; }
     }
-    return (int)edges.size() - (int)verts.size() + comps;
+    // vertices - components = merges
+    return edges - merges;
 }
 
 std::vector<double> default_deg(const Graph& g) {
@@ -271,13 +278,18 @@ std::vector<double> default_deg(const Graph& g) {
     auto subs = subgraphs(g);
     auto ch = chords(g);
     // reduced-graph edge lists of every forest: (line id, node a, node b)
-    std::vector<std::vector<std::vector<std::array<int, 3>>>> structs;
+    std::vector<std::vector<PieceEdges>> structs;
     for (uint32_t mask : forests(subs)) {
-        std::vector<std::vector<std::array<int, 3>>> st;
+        std::vector<PieceEdges> st;
         for (auto& p : term_pieces(g, subs, mask, -1)) {
-            std::vector<std::array<int, 3>> E;
-            for (int j = 0; j < (int)p.lines.size(); ++j) E.push_back({p.lines[j], j, j + 1});
-            for (auto& c : p.chords) E.push_back({2 * n + c[0], c[1], c[2]});
+            PieceEdges E;
+            auto add = [&](int id, int a, int b) {
+                if (E.ne == 2 * QA_MAXL || a >= 2 * QA_MAXL + 2 || b >= 2 * QA_MAXL + 2)
+                    throw std::runtime_error("default_deg: piece too large");
+                E.id[E.ne] = id; E.a[E.ne] = a; E.b[E.ne] = b; ++E.ne;
+            };
+            for (int j = 0; j < (int)p.lines.size(); ++j) add(p.lines[j], j, j + 1);
+            for (auto& c : p.chords) add(2 * n + c[0], c[1], c[2]);
             st.push_back(E);
         }
         structs.push_back(st);
@@ -295,11 +307,7 @@ std::vector<double> default_deg(const Graph& g) {
         double best = 1e300;
         for (auto& st : structs) {
             int h = 0;
-            for (auto& E : st) {
-                std::vector<std::array<int, 2>> ed;
-                for (auto& e : E) if (c >> e[0] & 1) ed.push_back({e[1], e[2]});
-                h += cyclomatic(ed);
-            }
+            for (auto& E : st) h += cyclomatic(E, c);
             best = std::min(best, -(2.0 * h - nph - 0.5 * nel));
         }
         D[s] = std::max(0.5, best);
@@ -352,12 +360,15 @@ std::vector<double> dlogw(const std::vector<double>& D, int M) {
 // contributes tr(s eps^q) = 0 (q odd) or 2 s (-1)^(q/2).  Both chiralities
 // give the same value, so Tr = 2 * 2^pairs * prod over cycles.
 
+// labels of contracted pairs: 1..kMaxLabel-1 (photons, Wick pairs, projector indices)
+constexpr int kMaxLabel = 32;
+
 long long dirac_trace(const int* sym, int L) {
     if (L == 0) return 4;
     if (L % 2) return 0;
     if (L > 62) throw std::runtime_error("dirac_trace: string too long");
-    int first[64];
-    for (int l = 0; l < 64; ++l) first[l] = -1;
+    int first[kMaxLabel];
+    for (int l = 0; l < kMaxLabel; ++l) first[l] = -1;
     uint8_t partner[128];
     int8_t eps[128];   // 0: delta link; +1 / -1: eps link traversed forward / backward from this node
     int nch = 0;
@@ -368,7 +379,7 @@ long long dirac_trace(const int* sym, int L) {
             eps[2 * i] = eps[2 * i + 1] = 0;
             continue;
         }
-        if (s >= 64) throw std::runtime_error("dirac_trace: label too large");
+        if (s >= kMaxLabel) throw std::runtime_error("dirac_trace: label too large");
         if (first[s] < 0) { first[s] = i; continue; }
         const int a = first[s], b = i;
         first[s] = -2;
@@ -384,7 +395,7 @@ long long dirac_trace(const int* sym, int L) {
             eps[2 * a + 1] = 1; eps[2 * b + 1] = -1;
         }
     }
-    for (int l = 0; l < 64; ++l)
+    for (int l = 0; l < kMaxLabel; ++l)
         if (first[l] >= 0) throw std::runtime_error("dirac_trace: unpaired label");
     uint8_t chain[128];
     for (int i = 0; i < L; ++i) {

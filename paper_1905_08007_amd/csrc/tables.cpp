@@ -12,7 +12,6 @@
 #include <cstdio>
 #include <stdexcept>
 #include <string>
-#include <unordered_map>
 
 #include "host.h"
 
@@ -86,41 +85,21 @@ void pairings_rec(const std::vector<int>& slots, size_t i, std::vector<int>& use
     used[i] = 0;
 }
 
-// Trace with p-slash p-slash = 1 reduction and a per-thread memo keyed by
-// the reduced string with labels renumbered by first appearance.
-long long cached_trace(const std::vector<int>& in) {
-    static thread_local std::unordered_map<std::string, long long> memo;
+// Trace after the p-slash p-slash = 1 reduction (adjacent, and cyclic at the
+// ends).  The spinor-wiring trace is linear in the string length, cheaper than
+// any lookup keyed by the string.
+long long reduced_trace(const std::vector<int>& in) {
     int red[64];
     int n = 0;
     for (int v : in) {
         if (v == 0 && n > 0 && red[n - 1] == 0) { --n; continue; }
+        if (n == 64) throw std::runtime_error("trace: string too long");
         red[n++] = v;
     }
-    while (n >= 2 && red[0] == 0 && red[n - 1] == 0) {   // cyclic p p = 1
-        for (int i = 1; i < n - 1; ++i) red[i - 1] = red[i];
-        n -= 2;
-    }
-    if (n % 2) return 0;
-    char key[64];
-    int map[64];
-    for (int i = 0; i < 64; ++i) map[i] = 0;
-    int next = 1;
-    for (int i = 0; i < n; ++i) {
-        int v = red[i];
-        if (v > 0) {
-            if (!map[v]) map[v] = next++;
-            v = map[v];
-        }
-        key[i] = (char)(v + 1);
-        red[i] = v;
-    }
-    std::string k(key, key + n);
-    auto it = memo.find(k);
-    if (it != memo.end()) return it->second;
-    if (memo.size() > 4000000) memo.clear();
-    long long t = dirac_trace(red, n);
-    memo.emplace(std::move(k), t);
-    return t;
+    int lo = 0;
+    while (n - lo >= 2 && red[lo] == 0 && red[n - 1] == 0) { ++lo; --n; }
+    if ((n - lo) % 2) return 0;
+    return dirac_trace(red + lo, n - lo);
 }
 
 }  // namespace
@@ -185,29 +164,34 @@ Table build_table(const Piece& p, int opvar, uint32_t variant, int nloops, int p
             const size_t n1 = tab.has_q && r > 0 ? size_t(r) << (r - 1) : 0;
             b.coef.assign(n0 + n1, 0.0);
             // choice per slot: -1 m (scalar), 0 pslash, LAB_NU derivative gamma, or the pair label
-            std::vector<int> sym;
+            // the string after the projector's prefix is the same for every
+            // projector term but for the symbol at the external vertex
+            std::vector<int> sym, body;
             sym.reserve(64);
+            body.reserve(64);
             auto eval = [&](const std::vector<int>& choice, bool qterm) -> double {
+                body.clear();
+                int ext_at = -1;
+                for (int j = (int)p.nodes.size() - 1; j >= 0; --j) {
+                    const auto& nd = p.nodes[j];
+                    if (nd.vtype == 0) body.push_back(plab[nd.photon]);
+                    else if (nd.vtype == 1) { ext_at = (int)body.size(); body.push_back(0); }
+                    else if (pseudo_at[j] >= 0) {
+                        int c = choice[pseudo_at[j]];
+                        if (c >= 0) body.push_back(c);
+                    }
+                    if (j > 0) {
+                        int c = choice[j - 1];
+                        if (c >= 0) body.push_back(c);
+                    }
+                }
                 long long acc = 0;
                 for (auto& pt : proj) {
                     if (pt.q != qterm) continue;
-                    sym.clear();
-                    for (int i = 0; i < pt.nprefix; ++i) sym.push_back(pt.prefix[i]);
-                    for (int j = (int)p.nodes.size() - 1; j >= 0; --j) {
-                        const auto& nd = p.nodes[j];
-                        if (nd.vtype == 0) sym.push_back(plab[nd.photon]);
-                        else if (nd.vtype == 1) sym.push_back(pt.ext);
-                        else if (pseudo_at[j] >= 0) {
-                            int c = choice[pseudo_at[j]];
-                            if (c >= 0) sym.push_back(c);
-                        }
-                        if (j > 0) {
-                            int c = choice[j - 1];
-                            if (c >= 0) sym.push_back(c);
-                        }
-                    }
-                    long long tr = cached_trace(sym);
-                    acc += (long long)pt.num * tr;
+                    if (ext_at >= 0) body[ext_at] = pt.ext;
+                    sym.assign(pt.prefix, pt.prefix + pt.nprefix);
+                    sym.insert(sym.end(), body.begin(), body.end());
+                    acc += (long long)pt.num * reduced_trace(sym);
                 }
                 return (double)acc;
             };

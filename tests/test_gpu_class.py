@@ -1,5 +1,6 @@
 """GPU parity at the benchmark's scale: every graph of the 5-loop class
-(5,0,0), every graph at 1..4 loops for the sampler, the batched form's sums
+(5,0,0), four graphs of each other 5-loop class, every graph at 1..4 loops
+for the sampler, the batched form's sums
 against the oracle's on the same Philox points, and the configurations'
 integrals (1 and 2 loops at their full sample counts)."""
 import json
@@ -104,6 +105,71 @@ def test_class500_batched_sums_match_oracle():
         tol = 1e-10 * math.fsum(abs(w) for w in ws)
         assert abs(s1 - math.fsum(ws)) <= tol, (gi, s1, math.fsum(ws))
         assert abs(s2 - math.fsum(w * w for w in ws)) <= 2e-10 * math.fsum(w * w for w in ws), gi
+
+
+def test_other_classes_sample_eval_and_sums():
+    """Four graphs of each of the other eight 5-loop classes (Table 1), taken
+    together as one set: the library's enumeration gives the oracle's graphs
+    at the same class indices; sector, z, log p and f of the precision form
+    within 1e-10 of the oracle at the first three points of the set's stream;
+    the estimate covers the FP64 error; the batched sums match the oracle's."""
+    gold = _gold("oracle_5loop_classes.json")
+    picks = []
+    by_cls = {}
+    for gg in gold["graphs"]:
+        c = tuple(gg["class"])
+        if c not in by_cls:
+            by_cls[c] = P.enumerate_graphs(5, *c)
+        g = by_cls[c][gg["index"]]
+        assert g.x == gg["x"] and list(g.mate)[:11] == gg["mate"] and g.mult == gg["mult"], (c, gg["index"])
+        picks.append(g)
+    s = P.build_forests(picks)
+    img = P.upload(s, P.pdf_create(s))
+    for gi, gg in enumerate(gold["graphs"]):
+        pts = gg["philox"]
+        z, lp, sec = P.sample_pdf(img, gi, gold["seed"], gold["tag"], 0, len(pts), want_sector=True)
+        fb, eb, flag = P.eval_integrand(img, gi, z, P.QA_FP64_BOUND)
+        fd, ed, _ = P.eval_integrand(img, gi, z, P.QA_DD)
+        fe, ee, _ = P.eval_integrand(img, gi, z, P.QA_FP64_EST)
+        torch.cuda.synchronize()
+        zc, lpc, secc = z.cpu().numpy(), lp.cpu().numpy(), sec.cpu().numpy()
+        fb, eb, flag, fd, ed, fe, ee = (t.cpu().numpy() for t in (fb, eb, flag, fd, ed, fe, ee))
+        for i, pt in enumerate(pts):
+            assert list(secc[:, i]) == pt["order"], (gi, i)
+            assert np.max(np.abs(zc[:, i] - pt["z"]) / np.array(pt["z"])) < 1e-12, (gi, i)
+            assert abs(lpc[i] - pt["logp"]) < 1e-11 * max(1.0, abs(pt["logp"])), (gi, i)
+            v = pt["f"]
+            scale = abs(v) if v != 0 else pt["terms_abs"]
+            final = fd[i] if flag[i] else fb[i]
+            assert abs(final - v) <= 1e-10 * scale + 1e-13 * pt["terms_abs"], (gi, i, final, v, flag[i])
+            assert abs(fe[i] - v) <= ee[i] + 1e-10 * scale, (gi, i, fe[i], v, ee[i])
+    n = len(gold["graphs"][0]["philox"])
+    a = P.read_acc(P.integrate(s, img, np.full(len(picks), n, dtype=np.uint64), seed=gold["seed"], tag=gold["tag"],
+                               tile=64))
+    torch.cuda.synchronize()
+    for gi, gg in enumerate(gold["graphs"]):
+        ws = [pt["w"] for pt in gg["philox"]]
+        x = a[gi]
+        assert int(x["n"]) == n and int(x["n_bad"]) == 0
+        s1 = x["s1_hi"] + x["s1_lo"]
+        assert abs(s1 - math.fsum(ws)) <= 1e-10 * math.fsum(abs(w) for w in ws), (gi, s1, math.fsum(ws))
+
+
+def test_class_flow_in_parts_sums_to_the_class():
+    """The class-by-class flow on class (5,0,0) split into parts of at most 32
+    graphs (three graph sets with their own Philox keys): the Neyman budgets
+    of the parts add up to the class's samples, the class record is the sum
+    of the per-graph records (value, and sigma in quadrature), and the set
+    total over the classes run is that record."""
+    from paper_1905_08007_amd import classes as CL
+    res, total = CL.integrate_all(3, 4000, classes=[(5, 0, 0)], pilot_per_graph=1024, chunks=2, max_graphs=32)
+    per, tot, sec = res[(5, 0, 0)]
+    assert len(per) == 73 and sec > 0
+    assert int(tot["n"]) == 73 * 4000 and int(tot["n_bad"]) == 0
+    assert np.all(np.isfinite(per["value"])) and np.all(per["sigma"] > 0)
+    assert abs(tot["value"] - math.fsum(per["value"])) <= 1e-12 * math.fsum(abs(per["value"]))
+    assert abs(tot["sigma"] - math.sqrt(math.fsum(per["sigma"] ** 2))) <= 1e-12 * tot["sigma"]
+    assert total["value"] == tot["value"] and total["sigma"] == tot["sigma"]
 
 
 def test_eval_4loop_interior_many_graphs():

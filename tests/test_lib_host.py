@@ -25,7 +25,7 @@ def test_exports_every_declared_symbol():
         assert hasattr(L, n), n
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
 def test_graph_lists_match_oracle(n):
     mine = [P.graph_dict(g) for g in P.enumerate_graphs(n)]
     theirs = GR.enumerate_graphs(n)
@@ -36,6 +36,10 @@ def test_class_filter_5loop():
     gs = P.enumerate_graphs(5, 5, 0, 0)
     assert len(gs) == 73
     assert len(P.enumerate_graphs(5)) == 3213
+    # every class filter returns the class's graphs of the full list, in order
+    full = [P.graph_dict(g) for g in P.enumerate_graphs(5)]
+    for c in {tuple(g["cls"]) for g in full}:
+        assert [P.graph_dict(g) for g in P.enumerate_graphs(5, *c)] == [g for g in full if tuple(g["cls"]) == c]
 
 
 @pytest.mark.parametrize("n,count", [(2, 4), (3, 28), (4, 40)])

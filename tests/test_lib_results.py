@@ -66,6 +66,31 @@ def test_combine_reproduces_eq2():
         P.combine(runs)
 
 
+def test_sum_results_matches_oracle_set_total():
+    from test_oracle_mc import TABLE1
+    rng = np.random.default_rng(5)
+    parts = np.zeros(9, dtype=P.RESULT_DTYPE)
+    parts["value"] = rng.normal(size=9) * 3
+    parts["sigma"] = rng.uniform(0.01, 0.2, size=9)
+    parts["n"] = rng.integers(10, 1000, size=9)
+    out = P.sum_results(parts)
+    v, e = mc.set_total(list(zip(parts["value"], parts["sigma"])))
+    assert abs(out["value"] - v) <= 1e-14 * max(1.0, abs(v)) and abs(out["sigma"] - e) <= 1e-15 * e
+    assert int(out["n"]) == int(parts["n"].sum())
+    # Table 1: the nine Calc 1 class rows against Calc 1's total 6.739(132)
+    rows = np.zeros(9, dtype=P.RESULT_DTYPE)
+    rows["value"] = [TABLE1[c][1][0] for c in sorted(TABLE1)]
+    rows["sigma"] = [TABLE1[c][1][1] for c in sorted(TABLE1)]
+    out = P.sum_results(rows)
+    assert abs(out["value"] - 6.739) < 0.005 and abs(out["sigma"] - 0.132) < 0.001
+    rows["sigma"][3] = float("nan")
+    with pytest.raises(RuntimeError):
+        P.sum_results(rows)
+    rows["sigma"][3] = -0.1
+    with pytest.raises(RuntimeError):
+        P.sum_results(rows)
+
+
 def test_pdf_with_and_tune():
     gs = P.enumerate_graphs(2)
     s = P.build_forests(gs, 2)

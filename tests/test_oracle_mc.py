@@ -67,3 +67,20 @@ def test_combine_reproduces_table1_rows(cls):
     ss = [e for _, e in grid]
     assert min(vs) - _half_unit(val) <= val <= max(vs) + _half_unit(val), (cls, min(vs), max(vs), val)
     assert min(ss) - _half_unit(sig) <= sig <= max(ss) + _half_unit(sig), (cls, min(ss), max(ss), sig)
+
+
+@pytest.mark.parametrize("calc", [1, 2])
+def test_set_total_adds_table1_classes_to_calc_totals(calc):
+    """Table 1's nine class rows of one calculation add up to that calculation's
+    total (section "Preliminary numerical results": Calc 1 6.739(132), Calc 2
+    6.905(220)): mc.set_total's value lies within the summed half-units of the
+    printed rows (plus half a unit of the printed total) and its sigma within
+    the range the rounding box of the printed sigmas allows."""
+    total = {1: (6.739, 0.132), 2: (6.905, 0.220)}[calc]
+    rows = [TABLE1[c][calc] for c in sorted(TABLE1)]
+    v, s = mc.set_total(rows)
+    assert abs(v - total[0]) <= sum(_half_unit(a) for a, _ in rows) + _half_unit(total[0])
+    lo = mc.set_total([(a, e - _half_unit(e)) for a, e in rows])[1]
+    hi = mc.set_total([(a, e + _half_unit(e)) for a, e in rows])[1]
+    h = _half_unit(total[1])
+    assert lo - h <= total[1] <= hi + h and lo <= s <= hi
