@@ -13,8 +13,8 @@ same Philox stream).  Tile and grid are autotuned before the timed steps.
 Prints one JSON line: metric, value (evals/s), ms_per_step, the roofline of
 the fused kernel (FP64 flops of the integrand / its HIP-event time, against
 the FP64 vector peak, dense and with the folds priced at their nonzero
-coefficients; traffic from the committed counter record while the kernel is
-unchanged), per-graph results with a tail check, the oracle timed on the
+coefficients; traffic and the counted FP64 rate from the committed counter
+record while the kernel is unchanged), per-graph results with a tail check, the oracle timed on the
 host's cores (after the GPU work), and the plain per-graph FP64 path timed on
 the same GPU.
 """
@@ -87,10 +87,16 @@ def oracle_baseline(seconds, cores):
             "host_cores": os.cpu_count(), "cpu_model": model}
 
 
-def measured_traffic(samples_per_launch):
-    """HBM-side bytes of one fused launch, from the committed FETCH_SIZE / WRITE_SIZE
-    passes (profiles/k_fused_traffic.json, scaled by a plain-copy calibration), or
-    None when the kernel sources changed since those counters were taken."""
+def note(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
+def committed_counters():
+    """The committed counter record of one fused launch (profiles/k_fused_traffic.json:
+    FETCH_SIZE / WRITE_SIZE scaled by a plain-copy calibration, and the FP64
+    instruction counts), or None when the kernel sources changed since those
+    counters were taken."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "k_fused_traffic.json")
@@ -105,7 +111,7 @@ def measured_traffic(samples_per_launch):
         return None
     if h.hexdigest() != rec["sources_sha256"]:
         return None
-    return rec["bytes_per_sample"] * samples_per_launch
+    return rec
 
 
 def plain_path(P, gset, img, graphs, per_graph, first):
@@ -160,6 +166,7 @@ def main():
     pdf = P.pdf_create(gset)
     img = P.upload(gset, pdf, device="cuda:0")
     setup_s = time.time() - t0
+    note(f"set-up {setup_s:.1f} s")
     ng = len(graphs)
     per = args.samples // ng
     budgets = np.full(ng, per, dtype=np.uint64)
@@ -171,6 +178,7 @@ def main():
     if args.tile == 0 and args.grid == 0:
         # pick tile and grid on a pilot share of the budgets (outside the timed region)
         args.tile, args.grid, tuned_ns = P.autotune(gset, img, budgets, SEED, 0, pilot=1 << 20)
+        note(f"autotuned: tile {args.tile}, grid {args.grid}")
     elif args.tile == 0:
         args.tile = 256
     work = torch.empty(P.work_bytes(gset, budgets, args.tile), dtype=torch.uint8, device="cuda:0")
@@ -190,6 +198,7 @@ def main():
         step += 1
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    note(f"{args.steps} timed steps: {dt:.2f} s")
 
     # per-graph results over the timed steps (the library merges the sums and
     # forms the estimates); tail check: each graph's per-sample sd after the
@@ -215,6 +224,10 @@ def main():
     evals_s = samples / dt
     sigma_gpu_hour = sigma * math.sqrt(dt / 3600.0)
     achieved = eval_flops_step * args.steps / (fused_ms * 1e-3) / 1e12
+    counters = committed_counters()
+    counted = None
+    if counters is not None and "f64_flops_per_sample" in counters:
+        counted = counters["f64_flops_per_sample"] * per * ng * args.steps / (fused_ms * 1e-3) / 1e12
     achieved_nz = eval_flops_nz_step * args.steps / (fused_ms * 1e-3) / 1e12
 
     plain = None
@@ -224,9 +237,11 @@ def main():
         # heavy-tailed weights is far better estimated by the batched run's N, so the
         # comparison at equal per-sample sigma is sigma_hour * sqrt(rate ratio).
         plain["sigma_per_gpu_hour_at_batched_variance"] = sigma_gpu_hour * math.sqrt(evals_s / plain["evals_per_s"])
+        note("plain path done")
 
     cpu = None
     if not args.no_cpu_baseline:   # after the GPU work: the oracle takes every host core it is given
+        note(f"oracle on {args.cpu_cores} host cores ...")
         cpu = oracle_baseline(args.cpu_seconds, args.cpu_cores)
 
     out = {
@@ -273,7 +288,11 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": measured_traffic(per * ng),
+            "traffic": None if counters is None else counters["bytes_per_sample"] * per * ng,
+            # FP64 arithmetic the kernel executes (rocprofv3 F64 instruction counts of the same launch,
+            # FMA as 2: value and round-off-estimate folds, both geometry passes), over the same time
+            "counted_achieved": counted,
+            "counted_frac": None if counted is None else counted / FP64_PEAK_TFLOPS,
         },
         "cpu_baseline": cpu,
     }
