@@ -359,7 +359,8 @@ __global__ void __launch_bounds__(1024) k_accumulate(const double* __restrict__ 
 // batched form: persistent waves over tiles (graph, sample range)
 
 struct Partial {
-    double s1_hi, s1_lo, s2_hi, s2_lo;
+    double s1_hi, s1_lo, s2_hi, s2_lo;   // over the points that passed the relative test, then (k_select)
+                                         // plus the candidates kept in FP64
     double s2g;              // sum of w^2 over points that passed the relative test
     uint64_t n, nflag, nbad;
 };
@@ -369,7 +370,7 @@ struct FlagEntry {
     double estw;      // FP64 error estimate of w
     double q, cond;   // ER variance and geometry conditioning of the FP64 pass
     double ip;        // 1 / p
-    double c1, c2;    // corrections written by the double-double pass
+    DD c1, c2;        // double-double pass: w and w^2 of the recomputed value
     uint32_t graph;
     uint8_t fixed;    // recomputed in double-double
     uint8_t residual; // double-double estimate still above 1e-10 of the scale
@@ -530,9 +531,14 @@ __global__ void __launch_bounds__(kFusedThreads, kFusedOcc) k_fused(const uint8_
                 }
             }
             if (act && good) {
-                s1 = s1 + dd(wv_);
-                s2 = s2 + two_prod(wv_, wv_);
-                if (!flagged) s2g += wv_ * wv_;
+                // a candidate enters the sums later, once: in FP64 if it is kept
+                // (k_select), in double-double if it is recomputed (k_reduce);
+                // its FP64 value may be off by many orders
+                if (!flagged) {
+                    s1 = s1 + dd(wv_);
+                    s2 = s2 + two_prod(wv_, wv_);
+                    s2g += wv_ * wv_;
+                }
                 ++n;
             } else if (act) {
                 ++bad;
@@ -556,8 +562,8 @@ __global__ void __launch_bounds__(kFusedThreads, kFusedOcc) k_fused(const uint8_
                 fe.q = qv;
                 fe.cond = cnd;
                 fe.ip = ipv;
-                fe.c1 = 0.0;
-                fe.c2 = 0.0;
+                fe.c1 = DD{0.0, 0.0};
+                fe.c2 = DD{0.0, 0.0};
                 fe.graph = g;
                 fe.fixed = 0;
                 fe.residual = 0;
@@ -636,6 +642,7 @@ __global__ void __launch_bounds__(64) k_select(Work w) {
     for (uint32_t t = blockIdx.x; t < nr; t += gridDim.x) {
         const uint32_t nf = w.nflag[t];
         uint32_t cnt = 0;
+        DD k1{0.0, 0.0}, k2{0.0, 0.0};
         for (uint32_t b = 0; b < nf; b += 64) {
             const uint32_t e = b + lane;
             bool need = false;
@@ -643,8 +650,22 @@ __global__ void __launch_bounds__(64) k_select(Work w) {
                 FlagEntry& fe = w.flags[(uint64_t)t * w.tile + e];
                 need = needs_dd(fe, w.scale);
                 fe.fixed = need;
+                if (!need) {
+                    k1 = k1 + dd(fe.w);
+                    k2 = k2 + two_prod(fe.w, fe.w);
+                }
             }
             cnt += __popcll(__ballot(need));
+        }
+        if (nf) {
+            k1 = wave_sum_dd(k1);
+            k2 = wave_sum_dd(k2);
+            if (lane == 0) {
+                Partial& pr = w.partial[t];
+                const DD a1 = DD{pr.s1_hi, pr.s1_lo} + k1, a2 = DD{pr.s2_hi, pr.s2_lo} + k2;
+                pr.s1_hi = a1.hi; pr.s1_lo = a1.lo;
+                pr.s2_hi = a2.hi; pr.s2_lo = a2.lo;
+            }
         }
         if (lane == 0) w.nsel[t] = cnt;
     }
@@ -763,8 +784,9 @@ __global__ void __launch_bounds__(64) k_fix_dd(const uint8_t* __restrict__ img_,
     }
 }
 
-// per selected entry: f = sum of its slices (in order); corrections of w and
-// w^2 and the residual test
+// per selected entry: f = sum of its slices (in order), its double-double w
+// and w^2 (k_reduce adds them: the entry's FP64 value never entered the sums,
+// so no correction has to cancel a possibly huge FP64 w) and the residual test
 __global__ void __launch_bounds__(256) k_fix_combine(Work w) {
     const uint32_t total = w.counter[kCSel], ns = w.counter[kCSlices];
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
@@ -775,10 +797,8 @@ __global__ void __launch_bounds__(256) k_fix_combine(Work w) {
         fe.residual = !(est_dd(fe.q, fmax(w.fcond[e], fe.cond), fdd) * ip <=
                         1e-10 * fmax(fabs(fdd) * ip, w.scale[fe.graph]));
         const DD wd = r * ip;
-        const DD d1 = wd - dd(fe.w);
-        const DD d2 = wd * wd - two_prod(fe.w, fe.w);
-        fe.c1 = d1.hi + d1.lo;
-        fe.c2 = d2.hi + d2.lo;
+        fe.c1 = wd;
+        fe.c2 = wd * wd;
     }
 }
 
@@ -801,8 +821,8 @@ __global__ void __launch_bounds__(64) k_reduce(Work w, qa_acc* acc) {
     const uint32_t e0 = w.seloff[a - t0], e1 = w.seloff[b - 1 - t0] + w.nsel[b - 1 - t0];
     for (uint32_t e = e0 + lane; e < e1; e += 64) {
         const FlagEntry& fe = w.flags[w.sel[e]];
-        s1 = s1 + dd(fe.c1);
-        s2 = s2 + dd(fe.c2);
+        s1 = s1 + fe.c1;
+        s2 = s2 + fe.c2;
         nr += fe.residual;
     }
     s1 = wave_sum_dd(s1);
