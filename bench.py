@@ -153,8 +153,8 @@ def main():
                     help="samples per graph of the plain per-graph FP64 comparison (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              "the hot path shards by graph / sample range without communication, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the hot path shards by graph set and "
+              "sample range without communication, so run one process per GPU on its own share", file=sys.stderr)
         sys.exit(2)
 
     import torch

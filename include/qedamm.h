@@ -191,8 +191,9 @@ int qa_pdf_dlogw(const qa_pdf* p, uint32_t graph, double* out);
  * its W table is rebuilt.  The other graphs keep base's tables. */
 int qa_pdf_with(const qa_pdf* base, uint32_t graph, const double* deg, qa_pdf** out);
 
-/* One pilot step on graph `graph`'s exponents (the benchmark spec's differentiation
- * form; production stays nonadaptive with the frozen result).  The exponents
+/* One pilot step on graph `graph`'s exponents (the differentiation form:
+ * pilot gradients move the exponents, production stays nonadaptive with the
+ * frozen result).  The exponents
  * move by one shift per set size: theta_c = -step * g_c / max_c |g_c| with
  * g_c = sum over |S| = c of grad[S] (grad: host, 2^(3n) doubles, the
  * gradient d E[w^2] / d Deg(S) from qa_variance_gradient), c = 1 .. 3n-1,

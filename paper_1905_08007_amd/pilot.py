@@ -59,3 +59,72 @@ def production(gset, img, seed, total, pilot_per_graph, floor_frac=0.25, pilot_t
             log(f"production chunk {c + 1}/{chunks}: {tot['value']:.6g} +- {tot['sigma']:.3g} over {int(tot['n'])} samples")
     per, tot = results(gset, merged)
     return per, tot, budgets
+
+
+def main(argv=None):
+    """Pilot with the backward kernel -> exponent steps -> frozen production,
+    for the default and the tuned exponents side by side, with an independent
+    check of each PDF's per-sample spread (key tag 3).
+    Usage: python -m paper_1905_08007_amd.pilot --loops 4 --seed 4 --steps 3"""
+    import argparse
+    import json
+    import time
+    import torch
+    from . import acc_read, build_forests, enumerate_graphs, integrate, pdf_create, upload, work_bytes
+    ap = argparse.ArgumentParser(description="pilot -> exponent steps -> frozen production")
+    ap.add_argument("--loops", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--pilot-samples", type=int, default=1 << 20, help="per graph and step")
+    ap.add_argument("--step-size", type=float, default=0.25)
+    ap.add_argument("--check-samples", type=int, default=1 << 21, help="per graph, independent key")
+    ap.add_argument("--total", type=float, default=1e10, help="production samples over the set")
+    ap.add_argument("--chunks", type=int, default=8)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    t0 = time.time()
+    gs = enumerate_graphs(a.loops)
+    s = build_forests(gs)
+    p0 = pdf_create(s)
+    img0 = upload(s, p0, device="cuda:0")
+    ng = len(gs)
+    mult = np.array([g.mult for g in gs], dtype=float)
+    log(f"{a.loops} loops, {ng} graphs: set-up {time.time() - t0:.1f} s")
+    work = torch.empty(work_bytes(s, np.full(ng, 1 << 25, dtype=np.uint64), 256), dtype=torch.uint8, device="cuda:0")
+
+    def check(img, label):
+        per, tot = acc_read(s, integrate(s, img, np.full(ng, a.check_samples, dtype=np.uint64), a.seed, 3, work=work))
+        spread = float(np.sum(per["sd"] * mult))
+        log(f"{label} exponents: independent check {tot['value']:.5g} +- {tot['sigma']:.4g}; "
+            f"sum over graphs of mu * sd(w) = {spread:.4g}")
+        return {"value": float(tot["value"]), "sigma": float(tot["sigma"]), "sum_mu_sd": spread}
+
+    rec = {"loops": a.loops, "seed": a.seed, "check_default": check(img0, "default")}
+    t1 = time.time()
+    p1, img1, hist = tune(s, p0, img0, a.seed, a.pilot_samples, a.steps, a.step_size, log=log)
+    rec["pilot_seconds"] = time.time() - t1
+    rec["pilot_m2"] = [float(np.sum(h)) for h in hist]
+    rec["check_tuned"] = check(img1, "tuned")
+    for label, img in (("tuned", img1), ("default", img0)):
+        t2 = time.time()
+        per, tot, _ = production(s, img, a.seed, a.total, 1 << 20, work=work, chunks=a.chunks, log=log)
+        torch.cuda.synchronize()
+        worst = int(np.argmax(per["sigma"]))
+        rec[f"production_{label}"] = {"value": float(tot["value"]), "sigma": float(tot["sigma"]), "n": int(tot["n"]),
+                                      "seconds": time.time() - t2, "largest_sigma_graph": worst,
+                                      "largest_sigma": float(per["sigma"][worst])}
+        log(f"production ({label} exponents, {a.total:.3g} samples): {tot['value']:.5f} +- {tot['sigma']:.5g}; "
+            f"largest per-graph sigma {float(per['sigma'][worst]):.4g} (graph {worst}); {time.time() - t2:.0f} s")
+    if a.out:
+        with open(a.out, "w") as fh:
+            json.dump(rec, fh)
+    return 0
+
+
+if __name__ == "__main__":
+    import sys
+    sys.exit(main())
