@@ -15,8 +15,10 @@ the fused kernel (FP64 flops of the integrand / its HIP-event time, against
 the FP64 vector peak, dense and with the folds priced at their nonzero
 coefficients; traffic and the counted FP64 rate from the committed counter
 record while the kernel is unchanged), per-graph results with a tail check, the oracle timed on the
-host's cores (after the GPU work), and the plain per-graph FP64 path timed on
-the same GPU.
+host's cores (after the GPU work), the plain per-graph FP64 path timed on
+the same GPU, and, outside the timed region, the method's production
+configuration (exponents tuned by three pilot steps, Neyman budgets) over as
+many samples, for its sigma per GPU-hour.
 """
 import argparse
 import json
@@ -114,6 +116,34 @@ def committed_counters():
     return rec
 
 
+def tuned_neyman(P, gset, pdf, img, args, samples):
+    """The production configuration of the method, outside the timed region:
+    three pilot steps of the exponents (backward kernel, 2^20 samples per graph
+    and step, key tag 1), frozen; Neyman budgets from a pilot of the frozen PDFs
+    (2^20 per graph, tag 1); then one batched call over as many samples as the
+    timed steps drew (tag 4), timed on its own.  Returns its class value, sigma
+    and sigma per GPU-hour at that time, next to which the timed steps'
+    uniform-budget figures stand (both from the same number of samples of
+    heavy-tailed weights: long runs compare them better)."""
+    import torch
+    from paper_1905_08007_amd import pilot as PL
+    ng = len(gset)
+    t0 = time.perf_counter()
+    _, img1, _ = PL.tune(gset, pdf, img, SEED, 1 << 20, args.tune_steps, 0.25)
+    pil = P.read_acc(P.integrate(gset, img1, np.full(ng, 1 << 20, dtype=np.uint64), SEED, 1))
+    budgets = P.allocate_budgets(gset, pil, int(samples), int(0.25 * samples / ng))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    acc = P.integrate(gset, img1, budgets, SEED, 4)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    per, tot = P.acc_read(gset, acc)
+    return {"tune_steps": args.tune_steps, "setup_seconds": t1 - t0, "samples": int(tot["n"]),
+            "seconds": dt, "class_value": float(tot["value"]), "class_sigma": float(tot["sigma"]),
+            "sigma_per_gpu_hour": float(tot["sigma"]) * math.sqrt(dt / 3600.0),
+            "budget_range": [int(budgets.min()), int(budgets.max())]}
+
+
 def plain_path(P, gset, img, graphs, per_graph, first):
     """The plain per-graph FP64 path on the same GPU, for comparison with the
     batched form: for each graph in turn qa_sample_pdf -> qa_eval_integrand
@@ -149,6 +179,8 @@ def main():
     ap.add_argument("--cpu-cores", type=int, default=min(16, os.cpu_count() or 1),
                     help="host cores (processes) of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-steps", type=int, default=3,
+                    help="pilot steps of the exponents for the tuned-PDF sigma comparison (0: skip it)")
     ap.add_argument("--plain-samples", type=int, default=1 << 16,
                     help="samples per graph of the plain per-graph FP64 comparison (0: skip)")
     args = ap.parse_args()
@@ -239,6 +271,11 @@ def main():
         plain["sigma_per_gpu_hour_at_batched_variance"] = sigma_gpu_hour * math.sqrt(evals_s / plain["evals_per_s"])
         note("plain path done")
 
+    tuned = None
+    if args.tune_steps > 0:
+        tuned = tuned_neyman(P, gset, pdf, img, args, per * ng * args.steps)
+        note("tuned exponents + Neyman budgets done")
+
     cpu = None
     if not args.no_cpu_baseline:   # after the GPU work: the oracle takes every host core it is given
         note(f"oracle on {args.cpu_cores} host cores ...")
@@ -268,6 +305,7 @@ def main():
             "seed": SEED,
             "sigma_per_gpu_hour": sigma_gpu_hour,
             "plain_per_graph_fp64": plain,
+            "tuned_exponents_neyman_budgets": tuned,
             "class_value": val,
             "class_sigma": sigma,
             "flagged_fraction": float(tot["n_flagged"]) / max(1.0, float(tot["n"])),
