@@ -247,13 +247,16 @@ int qa_accumulate(const double* f, const double* logp, uint64_t count, qa_acc* a
  * 1e-11 max(|w|, S_g), S_g the rms weight of graph g over the accurate
  * weights seen so far in the call (earlier rounds, and this round's points
  * with e <= 1e-11 |f|): the round-off of the accepted points stays below
- * 1e-11 of the weight scale.  acc.n_flagged counts the recomputed points,
+ * 1e-11 of the weight scale.  A point's weight enters the sums once: FP64
+ * when accepted, double-double when recomputed.  acc.n_flagged counts the
+ * recomputed points,
  * n_residual those whose double-double estimate still exceeds 1e-10 of that
  * scale.  Deterministic per-tile partials are reduced into acc (device, ng
  * records, overwritten).  The
  * work is split into rounds of at most 2^25 samples; one round is captured as
  * a hipGraph and replayed.  work (device) >= qa_work_bytes (same budgets and
- * tile; about 68 bytes per sample of a round).  tile = multiple of 64
+ * tile; about 116 bytes per sample of a round plus 0.6 GB of per-wave
+ * buffers).  tile = multiple of 64
  * (0 = 256); grid = persistent waves (0 = 16 per CU, max 4096; rounded up to
  * a multiple of 4: the fused pass runs workgroups of 4 waves).
  * fused_ms (host, nullable): receives the summed duration of the fused
