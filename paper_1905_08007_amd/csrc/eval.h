@@ -334,7 +334,7 @@ QA_HD T eval_block(const BH& b, const QA_RO qa_coef* c, VV<S> vars, bool has_q) 
 }
 
 // statically sized block (R free slots, R <= QA_STATIC_R): fully unrolled folds
-#define QA_STATIC_R 6
+#define QA_STATIC_R 8
 template <class T, class S, int R, int J> struct QStatic {
     QA_HD static void run(T& s, const QA_RO qa_coef* c, const T* A, VV<S> vars, const BH& b) {
         s = s + lift_to<T>(vars.ac(b.cidx(J))) * Fold<T, R - 1, J>::run(c + (1 << R) + J * (1 << (R - 1)), A);
@@ -555,6 +555,7 @@ QA_HD void eval_table(const QA_RO uint8_t* img, const QA_RO DevTable& tb, VV<S> 
                 case 4: group_static<BT, S, 4>(blocks, b0, b1, coefs, vars, hq, acc); break;
                 case 5: group_static<BT, S, 5>(blocks, b0, b1, coefs, vars, hq, acc); break;
                 case 6: group_static<BT, S, 6>(blocks, b0, b1, coefs, vars, hq, acc); break;
+                case 8: group_static<BT, S, 8>(blocks, b0, b1, coefs, vars, hq, acc); break;
                 default:
                     for (int bi = b0; bi < b1; ++bi) {
                         const BH b = load_bh(blocks[bi]);
