@@ -165,3 +165,27 @@ def test_merged_pdf_tables_match_oracle():
             assert np.array_equal(Wm, PD.w_table(Do, 3 * n - 1))
         with pytest.raises(RuntimeError):
             q.merged()
+
+
+def test_production_chunks_and_class_parts():
+    """Host logic of the production and class flows: the per-call share B keeps
+    every call within its sample bound and is the largest such share; the
+    class parts cover each class once, in enumeration order."""
+    from paper_1905_08007_amd import classes as CL
+    from paper_1905_08007_amd.pilot import chunk_size
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        b = rng.integers(1, 10 ** 9, size=int(rng.integers(1, 300))).astype(np.uint64)
+        cap = int(rng.integers(int(b.min()), int(b.sum()) + 1))
+        B = chunk_size(b, cap)
+        assert int(np.minimum(b, B).sum()) <= cap or B == 1
+        if B < int(b.max()):
+            assert int(np.minimum(b, B + 1).sum()) > cap
+    full = P.enumerate_graphs(5)
+    seen = []
+    for c in CL.CLASSES:
+        parts = CL.class_parts(c, max_graphs=100)
+        assert all(0 < len(p) <= 100 for p in parts)
+        seen += [P.graph_dict(g) for p in parts for g in p]
+    assert sorted(map(str, seen)) == sorted(str(P.graph_dict(g)) for g in full)
+    assert len(seen) == 3213
