@@ -248,7 +248,8 @@ int qa_accumulate(const double* f, const double* logp, uint64_t count, qa_acc* a
  * weights seen so far in the call (earlier rounds, and this round's points
  * with e <= 1e-11 |f|): the round-off of the accepted points stays below
  * 1e-11 of the weight scale.  A point's weight enters the sums once: FP64
- * when accepted, double-double when recomputed.  acc.n_flagged counts the
+ * when accepted, double-double when recomputed (a recomputed weight that is
+ * not finite counts in n_bad, as w = 0).  acc.n_flagged counts the
  * recomputed points,
  * n_residual those whose double-double estimate still exceeds 1e-10 of that
  * scale.  Deterministic per-tile partials are reduced into acc (device, ng

@@ -374,7 +374,8 @@ struct FlagEntry {
     uint32_t graph;
     uint8_t fixed;    // recomputed in double-double
     uint8_t residual; // double-double estimate still above 1e-10 of the scale
-    uint8_t pad[2];
+    uint8_t bad;      // double-double w or w^2 not finite: the point counts as w = 0 (n_bad)
+    uint8_t pad;
 };
 static_assert(sizeof(DD) == sizeof(ER), "the DD pass reuses the piece-result buffer of the fused pass");
 struct Work {
@@ -567,6 +568,7 @@ __global__ void __launch_bounds__(kFusedThreads, kFusedOcc) k_fused(const uint8_
                 fe.graph = g;
                 fe.fixed = 0;
                 fe.residual = 0;
+                fe.bad = 0;
             }
             nfl += tot;
             __syncthreads();
@@ -797,8 +799,12 @@ __global__ void __launch_bounds__(256) k_fix_combine(Work w) {
         fe.residual = !(est_dd(fe.q, fmax(w.fcond[e], fe.cond), fdd) * ip <=
                         1e-10 * fmax(fabs(fdd) * ip, w.scale[fe.graph]));
         const DD wd = r * ip;
-        fe.c1 = wd;
-        fe.c2 = wd * wd;
+        const DD w2 = wd * wd;
+        // as in the fused pass, a weight that is not finite counts as a drawn
+        // sample with w = 0 (moved from n to n_bad in k_reduce)
+        fe.bad = !(isfinite(wd.hi) && isfinite(wd.lo) && isfinite(w2.hi) && isfinite(w2.lo));
+        fe.c1 = fe.bad ? DD{0.0, 0.0} : wd;
+        fe.c2 = fe.bad ? DD{0.0, 0.0} : w2;
     }
 }
 
@@ -809,7 +815,7 @@ __global__ void __launch_bounds__(64) k_reduce(Work w, qa_acc* acc) {
     uint64_t a, b, t0;
     if (g >= w.ng || !round_tiles(w, g, a, b, t0)) return;
     DD s1{0.0, 0.0}, s2{0.0, 0.0};
-    uint64_t n = 0, nb = 0, nr = 0;
+    uint64_t n = 0, nb = 0, nr = 0, nfb = 0;
     for (uint64_t gt = a + lane; gt < b; gt += 64) {
         const Partial& p = w.partial[gt - t0];
         s1 = s1 + DD{p.s1_hi, p.s1_lo};
@@ -824,20 +830,22 @@ __global__ void __launch_bounds__(64) k_reduce(Work w, qa_acc* acc) {
         s1 = s1 + fe.c1;
         s2 = s2 + fe.c2;
         nr += fe.residual;
+        nfb += fe.bad;
     }
     s1 = wave_sum_dd(s1);
     s2 = wave_sum_dd(s2);
     n = wave_sum_u64(n);
     nb = wave_sum_u64(nb);
     nr = wave_sum_u64(nr);
+    nfb = wave_sum_u64(nfb);
     if (lane == 0) {
         s1 = DD{acc[g].s1_hi, acc[g].s1_lo} + s1;
         s2 = DD{acc[g].s2_hi, acc[g].s2_lo} + s2;
         acc[g].s1_hi = s1.hi; acc[g].s1_lo = s1.lo;
         acc[g].s2_hi = s2.hi; acc[g].s2_lo = s2.lo;
-        acc[g].n += n;
+        acc[g].n += n - nfb;   // recomputed points whose weight is not finite count as bad
         acc[g].n_flagged += e1 - e0;
-        acc[g].n_bad += nb;
+        acc[g].n_bad += nb + nfb;
         acc[g].n_residual += nr;
     }
 }
