@@ -8,28 +8,47 @@ only sequences the calls."""
 import numpy as np
 
 
-def tune(gset, pdf, img, seed, samples, steps, step_size, floor=0.5, tag=1, device="cuda:0", log=None):
+def tune(gset, pdf, img, seed, samples, steps, step_size, floor=0.5, tag=1, device="cuda:0", log=None,
+         guard=False, guard_tag=6):
     """`steps` pilot steps over every graph of the set.  A step draws fresh
     samples (tag `tag`, sample range advancing by `samples` per step) from the
     current PDFs, forms each graph's gradient d E[w^2] / d Deg and moves its
-    exponents by one step of at most `step_size` per set size.  Returns
-    (pdf, img, history) with history[k] = per-graph E[w^2] measured at step k
-    (before that step's move)."""
-    from . import upload, variance_gradient
+    exponents by one step of at most `step_size` per set size.  With guard,
+    each graph's move is kept only if E[w^2] = S2 / N measured on fresh samples
+    (tag `guard_tag`, `samples` per graph, the batched form) is lower under the
+    moved exponents than under the current ones.  Returns (pdf, img, history)
+    with history[k] = per-graph E[w^2] measured at step k (before its move)."""
+    from . import integrate, read_acc, upload, variance_gradient
+    ng = len(gset)
+
+    def second_moment(image, first):
+        a = read_acc(integrate(gset, image, np.full(ng, samples, dtype=np.uint64), seed, guard_tag, first=first))
+        n = (a["n"] + a["n_bad"]).astype(float)
+        return (a["s2_hi"] + a["s2_lo"]) / np.maximum(n, 1.0)
+
     hist = []
     first = 0
     for k in range(steps):
         m2s = []
         new = pdf
-        for g in range(len(gset)):
+        for g in range(ng):
             m2, grad = variance_gradient(pdf, img, g, seed, tag, first, samples)
             m2s.append(m2)
             new, _ = new.tune(g, grad, step_size, floor)
         hist.append(np.array(m2s))
+        img_new = upload(gset, new, device=device)
+        if guard:
+            before, after = second_moment(img, first), second_moment(img_new, first)
+            keep = after < before
+            for g in np.nonzero(~keep)[0]:
+                new = new.with_graph(int(g), pdf.tables(int(g))[0])
+            if not keep.all():
+                img_new = upload(gset, new, device=device)
+            if log:
+                log(f"pilot step {k + 1}/{steps}: moves kept for {int(keep.sum())} of {ng} graphs")
         if log:
             log(f"pilot step {k + 1}/{steps}: sum of per-graph E[w^2] = {np.sum(m2s):.6g}")
-        pdf = new
-        img = upload(gset, pdf, device=device)
+        pdf, img = new, img_new
         first += samples
     return pdf, img, hist
 
@@ -103,6 +122,7 @@ def main(argv=None):
     ap.add_argument("--chunks", type=int, default=8)
     ap.add_argument("--max-chunk-samples", type=float, default=0, help="> 0: calls of at most this many samples")
     ap.add_argument("--productions", default="tuned,default", help="which exponents get a production run")
+    ap.add_argument("--guard", action="store_true", help="keep a graph's move only if fresh samples confirm it")
     ap.add_argument("--out", default="")
     a = ap.parse_args(argv)
 
@@ -131,7 +151,7 @@ def main(argv=None):
 
     rec = {"loops": a.loops, "class": list(cls), "seed": a.seed, "check_default": check(img0, "default")}
     t1 = time.time()
-    p1, img1, hist = tune(s, p0, img0, a.seed, a.pilot_samples, a.steps, a.step_size, log=log)
+    p1, img1, hist = tune(s, p0, img0, a.seed, a.pilot_samples, a.steps, a.step_size, log=log, guard=a.guard)
     rec["pilot_seconds"] = time.time() - t1
     rec["pilot_m2"] = [float(np.sum(h)) for h in hist]
     rec["check_tuned"] = check(img1, "tuned")
