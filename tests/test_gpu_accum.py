@@ -77,30 +77,33 @@ def test_batched_sums_exact_around_a_garbage_fp64_weight():
 
 
 def test_pilot_tune_steps_and_guard():
-    """The pilot flow's sequencing on the 2-loop set: a tuned step changes the
-    exponents by one shift per set size (never below the floor), the guard
-    keeps a move only where paired fresh samples confirm it, and the frozen
-    PDFs integrate."""
+    """The pilot flow's sequencing on the 2-loop set: one tuned step shifts the
+    exponents by one amount per set size (floored at 1/2); two steps with and
+    without the guard (a move kept only where paired fresh samples confirm it)
+    give finite second moments and PDFs that integrate."""
     from paper_1905_08007_amd import pilot as PL
     gs = P.enumerate_graphs(2)
     s = P.build_forests(gs)
     p0 = P.pdf_create(s)
     img0 = P.upload(s, p0)
+    M = 6
+    pc = np.array([bin(x).count("1") for x in range(1 << M)])
+    inner = (pc > 0) & (pc < M)
+    p1, _, _ = PL.tune(s, p0, img0, 2, 1 << 14, 1, 0.25)
+    for g in range(len(gs)):
+        D0, _ = p0.tables(g)
+        D1, _ = p1.tables(g)
+        assert np.all(D1[inner] >= 0.5)
+        for c in range(1, M):
+            sel = inner & (pc == c) & (D1 > 0.5)
+            if sel.sum() > 1:
+                d = D1[sel] - D0[sel]
+                assert np.ptp(d) < 1e-12 and abs(d[0]) <= 0.25 + 1e-12
     for guard in (False, True):
-        p1, img1, hist = PL.tune(s, p0, img0, 2, 1 << 14, 2, 0.25, guard=guard)
+        p2, img2, hist = PL.tune(s, p0, img0, 2, 1 << 14, 2, 0.25, guard=guard)
         assert len(hist) == 2 and all(np.all(np.isfinite(h)) and np.all(h > 0) for h in hist)
-        M = 6
-        pc = np.array([bin(x).count("1") for x in range(1 << M)])
-        inner = (pc > 0) & (pc < M)
         for g in range(len(gs)):
-            D0, _ = p0.tables(g)
-            D1, _ = p1.tables(g)
-            assert np.all(D1[inner] >= 0.5)
-            d = D1[inner] - D0[inner]
-            for c in range(1, M):   # one shift per set size where the floor does not bind
-                sel = (pc[inner] == c) & (D1[inner] > 0.5)
-                if sel.sum() > 1:
-                    assert np.ptp(d[sel]) < 1e-12
-        per, tot, budgets = PL.production(s, img1, 2, 4e5, 1 << 12, chunks=2)
+            assert np.all(p2.tables(g)[0][inner] >= 0.5)
+        per, tot, budgets = PL.production(s, img2, 2, 4e5, 1 << 12, chunks=2)
         torch.cuda.synchronize()
         assert int(tot["n"]) == 400000 and np.isfinite(tot["value"]) and tot["sigma"] > 0
