@@ -681,7 +681,7 @@ static int pack(const qa_set* s, const qa_pdf* p, std::vector<uint8_t>& out) {
                     size_t c = 0;
                     // identical coefficient arrays within a table are stored once (a
                     // repeat then hits the scalar cache instead of streaming again)
-                    std::map<std::vector<double>, uint32_t> seen;
+                    std::map<std::vector<float>, uint32_t> seen;
                     for (size_t bi = 0; bi < tb.blocks.size(); ++bi) {
                         const Block& b = tb.blocks[bi];
                         DevBlock db{};

@@ -53,7 +53,8 @@ long long dirac_trace(const int* sym, int L);
 struct Block {
     int k, r;
     uint8_t bidx[QA_MAXK], aidx[QA_MAXR], cidx[QA_MAXR];
-    std::vector<double> coef;   // 2^r (Gamma_0) then r * 2^(r-1) (Gamma_1) when has_q
+    std::vector<float> coef;    // 2^r (Gamma_0) then r * 2^(r-1) (Gamma_1) when has_q; integers
+                                // below 2^24, exact in float (checked when the table is built)
 };
 struct Table {
     bool has_q = false;

@@ -102,6 +102,14 @@ long long reduced_trace(const std::vector<int>& in) {
     return dirac_trace(red + lo, n - lo);
 }
 
+// coefficients are integers over the table's common denominator; float holds
+// them exactly below 2^24, which every table here satisfies
+float exact_float(double v) {
+    const float f = (float)v;
+    if ((double)f != v) throw std::runtime_error("coefficient not exact in float");
+    return f;
+}
+
 }  // namespace
 
 Table build_table(const Piece& p, int opvar, uint32_t variant, int nloops, int part, int nparts) {
@@ -162,7 +170,7 @@ Table build_table(const Piece& p, int opvar, uint32_t variant, int nloops, int p
             }
             const size_t n0 = size_t(1) << r;
             const size_t n1 = tab.has_q && r > 0 ? size_t(r) << (r - 1) : 0;
-            b.coef.assign(n0 + n1, 0.0);
+            b.coef.assign(n0 + n1, 0.0f);
             // choice per slot: -1 m (scalar), 0 pslash, LAB_NU derivative gamma, or the pair label
             // the string after the projector's prefix is the same for every
             // projector term but for the symbol at the external vertex
@@ -208,7 +216,7 @@ Table build_table(const Piece& p, int opvar, uint32_t variant, int nloops, int p
                 }
                 if (!ok) continue;
                 double v = eval(choice, false);
-                b.coef[mask] = v;
+                b.coef[mask] = exact_float(v);
                 any |= v != 0.0;
             }
             if (tab.has_q) {
@@ -226,7 +234,7 @@ Table build_table(const Piece& p, int opvar, uint32_t variant, int nloops, int p
                         }
                         if (!ok) continue;
                         double v = eval(choice, true);
-                        b.coef[n0 + (size_t(jq) << (r - 1)) + mask] = v;
+                        b.coef[n0 + (size_t(jq) << (r - 1)) + mask] = exact_float(v);
                         any |= v != 0.0;
                     }
                 }
